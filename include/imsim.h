@@ -1,0 +1,128 @@
+/*
+ * imsim: Monte Carlo simulation of the independent cascade (IC) and linear
+ * threshold (LT) diffusion models on one gfx950 GPU, behind a C ABI.
+ *
+ * The operation (paper Section 2, "Diffusion Models" and "Influence
+ * Maximization"): given a directed graph G = (V, E) in CSR form (Section 3,
+ * "Data Structures"), a per-arc parameter (IC activation probability p_uv, or
+ * LT influence weight w_uv with sum_u w_uv <= 1 for every v), a seed set S and
+ * a number of trials T, run T independent diffusions from S and report, per
+ * trial, the number of nodes active at the end (seeds included), and per node
+ * the number of trials in which it ended active.  sigma(S) = total / T.
+ *
+ * Randomness is a pure function of (rng_seed, trial, arc or node):
+ *   H(seed, dom, t, id) = 32-bit half (t & 1) of word ((t & 7) >> 1) of
+ *   Philox4x64-10(counter = (id, t >> 3, 0, 0), key = (seed, dom))
+ *   (Salmon et al., SC'11).  dom = 1: IC coin of out-CSR arc id;
+ *   dom = 2: LT threshold hash of node id.
+ *   IC: arc e is live in trial t  iff  thr_e == 0xFFFFFFFF or H(seed,1,t,e) < thr_e.
+ *   LT: v joins in trial t        iff  (active in-weight, 2^-32 units) > H(seed,2,t,v).
+ * Every trial's final active set is therefore fixed by the inputs; the
+ * library computes it exactly, independent of schedule and launch shape.
+ *
+ * Conventions
+ *   - Functions return 0 (IMS_OK) or a negative IMS_E_* code; the message of
+ *     the last failure on the calling thread is ims_last_error().  No C++
+ *     exception crosses this boundary.  On failure, outputs are unspecified.
+ *   - "host" pointers are read during the call only.  "device" pointers are
+ *     caller-owned HBM (e.g. torch tensors); the library never frees or keeps
+ *     them past the call.
+ *   - Work is enqueued on `stream` (a hipStream_t, NULL = the null stream)
+ *     and returns before it finishes, unless stated otherwise.
+ *   - A graph handle owns its device copy of the graph and a workspace that
+ *     grows on demand; calls on one handle must not overlap in time.
+ *   - Trial t lives in word t / 64, bit t % 64.  Bit-masks are word-major:
+ *     mask[w * n + v].  Bits of trials >= T are zero in every output.
+ */
+#ifndef IMSIM_H
+#define IMSIM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    IMS_OK = 0,
+    IMS_E_INVALID_ARG = -1,   /* null pointer, T == 0, bad model, bad p or w */
+    IMS_E_INVALID_GRAPH = -2, /* offsets not monotone, offsets[0] != 0, index >= n, n or m too large */
+    IMS_E_WEIGHT_SUM = -3,    /* LT: sum of in-weights of a node above 2^32 (i.e. above 1) */
+    IMS_E_SEED_RANGE = -4,    /* a seed id >= n */
+    IMS_E_OOM = -5,           /* device allocation failed */
+    IMS_E_HIP = -6,           /* a HIP runtime call failed */
+    IMS_E_LEVEL_CAP = -7,     /* a run needed more steps than the graph allows (internal bug guard) */
+    IMS_E_UNSUPPORTED = -8    /* valid request outside this build's limits */
+};
+
+enum { IMS_MODEL_IC = 0, IMS_MODEL_LT = 1 };
+
+typedef struct ims_graph ims_graph;
+
+/* Thread-local text of the last failure ("" if none). */
+const char* ims_last_error(void);
+const char* ims_version(void);
+
+/* Parameter encoding (host arrays of length m).
+ * IC (Section 2: arc (u,v) succeeds with probability p_uv):
+ *   thr = min(floor(p * 2^32), 2^32 - 1), and thr == 2^32 - 1 means "always";
+ *   p must lie in [0, 1] (NaN rejected).
+ * LT (Section 2: in-weights with sum at most 1):
+ *   w = floor(w_real * 2^32) as uint64; w_real must lie in [0, 1]. */
+int ims_encode_p(const double* p, int64_t m, uint32_t* thr);
+int ims_encode_w(const double* w, int64_t m, uint64_t* w64);
+
+/* Host-side CSR check (Section 3, "Data Structures": out-neighbours of u are
+ * indices[offsets[u] .. offsets[u+1])): offsets[0] == 0, non-decreasing,
+ * offsets[n] == m, every index < n.  Needs no GPU. */
+int ims_validate_csr(int64_t n, int64_t m, const int64_t* offsets, const uint32_t* indices);
+
+/* Build a graph plan on the current device from host arrays.
+ *   offsets  host int64[n+1], indices host uint32[m]   (out-CSR; self-loops and
+ *            repeated arcs are allowed: a self-loop never fires, repeated IC arcs
+ *            draw independent coins, repeated LT arcs add their weights)
+ *   model    IMS_MODEL_IC: param = host uint32 thr[m] (see ims_encode_p)
+ *            IMS_MODEL_LT: param = host uint64 w[m]   (see ims_encode_w);
+ *            every node's in-weights must sum to at most 2^32.
+ * Parameters are in out-CSR order: the arc id of indices[e] is e.  Limits:
+ * n < 2^32, m < 2^32.  Synchronous; copies everything it needs. */
+int ims_graph_create(int64_t n, int64_t m, const int64_t* offsets, const uint32_t* indices,
+                     int model, const void* param, ims_graph** out);
+int ims_graph_destroy(ims_graph* g);
+int ims_graph_info(const ims_graph* g, int64_t* n, int64_t* m, int* model);
+
+/* Simulation options; NULL = automatic.  Any setting gives the same bits. */
+typedef struct ims_opts {
+    int direction;        /* IC only: 0 = auto, 1 = push only, 2 = pull only */
+    int32_t blocks_per_cu; /* persistent grid occupancy; 0 = auto */
+    double alpha;         /* IC direction switch: pull when frontier arc volume * alpha > unvisited arcs; 0 = default */
+} ims_opts;
+
+/* Run trials 0 .. n_trials-1 from one seed set (Section 2).
+ *   seeds         host uint32[n_seeds]; duplicates allowed (set semantics),
+ *                 every id must be < n; n_seeds may be 0.
+ *   n_trials      T >= 1, T <= 2^18.
+ *   trial_counts  device uint32[T]: |A_t|, seeds included.          required
+ *   node_counts   device uint32[n]: #{t : v in A_t}.                 optional (NULL)
+ *   total         device uint64[1]: sum_t |A_t|; sigma = total / T.  required
+ *   active_bits   device uint64[ceil(T/64) * n], word-major.         optional (NULL)
+ * Asynchronous on `stream`. */
+int ims_simulate(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_t n_trials,
+                 uint64_t rng_seed, const ims_opts* opts, uint32_t* trial_counts,
+                 uint32_t* node_counts, uint64_t* total, uint64_t* active_bits, void* stream);
+
+/* Status of the last run on this handle: out[0] = steps (IC frontier levels
+ * or LT sweeps) taken, out[1] = nonzero if the step guard fired.  Waits for
+ * `stream`. */
+int ims_graph_last_status(ims_graph* g, void* stream, uint32_t out[2]);
+
+/* Test hook: out[i] = H(rng_seed, domain, trials[i], ids[i]) for i < count,
+ * computed by the device hash.  Device arrays. */
+int ims_debug_hash(uint64_t rng_seed, uint64_t domain, const uint64_t* trials, const uint64_t* ids,
+                   uint32_t* out, int64_t count, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IMSIM_H */

@@ -1,0 +1,200 @@
+"""imsim: Monte Carlo IC / LT diffusion on one gfx950 GPU.
+
+A thin ctypes binding over libimsim.so (C ABI declared in include/imsim.h).
+PyTorch provides device memory and the stream; every step of the simulation
+runs in the library's HIP kernels.  There is no CPU fallback: importing this
+package without the built library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+# torch ships its own HIP runtime with the same SONAME as /opt/rocm's; loading
+# it first makes libimsim.so bind to that one copy, so both share devices,
+# streams and memory.
+import torch  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libimsim.so")
+
+IC, LT = 0, 1
+ERRORS = {0: "IMS_OK", -1: "IMS_E_INVALID_ARG", -2: "IMS_E_INVALID_GRAPH", -3: "IMS_E_WEIGHT_SUM",
+          -4: "IMS_E_SEED_RANGE", -5: "IMS_E_OOM", -6: "IMS_E_HIP", -7: "IMS_E_LEVEL_CAP",
+          -8: "IMS_E_UNSUPPORTED"}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2404_17059_amd.build` "
+                      "(this package has no CPU fallback)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_P = ctypes.c_void_p
+_i64, _u64, _u32, _int = ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("direction", ctypes.c_int), ("blocks_per_cu", ctypes.c_int32), ("alpha", ctypes.c_double)]
+
+
+def _sig(name, res, *args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = list(args)
+    return f
+
+
+_sig("ims_last_error", ctypes.c_char_p)
+_sig("ims_version", ctypes.c_char_p)
+_sig("ims_encode_p", _int, _P, _i64, _P)
+_sig("ims_encode_w", _int, _P, _i64, _P)
+_sig("ims_validate_csr", _int, _i64, _i64, _P, _P)
+_sig("ims_graph_create", _int, _i64, _i64, _P, _P, _int, _P, ctypes.POINTER(_P))
+_sig("ims_graph_destroy", _int, _P)
+_sig("ims_graph_info", _int, _P, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_int))
+_sig("ims_simulate", _int, _P, _P, _u32, _u32, _u64, ctypes.POINTER(Opts), _P, _P, _P, _P, _P)
+_sig("ims_graph_last_status", _int, _P, _P, _P)
+_sig("ims_debug_hash", _int, _u64, _u64, _P, _P, _P, _i64, _P)
+
+
+class ImsError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = _lib.ims_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _check(code: int, where: str) -> None:
+    if code != 0:
+        raise ImsError(code, where)
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def version() -> str:
+    return _lib.ims_version().decode()
+
+
+def encode_p(p) -> np.ndarray:
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    out = np.zeros(p.shape[0], dtype=np.uint32)
+    _check(_lib.ims_encode_p(_np_ptr(p), p.shape[0], _np_ptr(out)), "ims_encode_p")
+    return out
+
+
+def encode_w(w) -> np.ndarray:
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    out = np.zeros(w.shape[0], dtype=np.uint64)
+    _check(_lib.ims_encode_w(_np_ptr(w), w.shape[0], _np_ptr(out)), "ims_encode_w")
+    return out
+
+
+def validate_csr(n: int, offsets, indices) -> None:
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    indices = np.ascontiguousarray(indices, dtype=np.uint32)
+    _check(_lib.ims_validate_csr(n, indices.shape[0], _np_ptr(offsets), _np_ptr(indices)), "ims_validate_csr")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Graph:
+    """Device graph plan.  `param` is the real-valued per-arc parameter in
+    out-CSR order (IC probability or LT weight), encoded by the library, or an
+    already encoded array (uint32 thresholds / uint64 weights)."""
+
+    def __init__(self, n: int, offsets, indices, model: str, param):
+        self.n = int(n)
+        self.model = model
+        offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        indices = np.ascontiguousarray(indices, dtype=np.uint32)
+        self.m = int(indices.shape[0])
+        param = np.asarray(param)
+        if model == "ic":
+            enc = param if param.dtype == np.uint32 else encode_p(param)
+            enc = np.ascontiguousarray(enc, dtype=np.uint32)
+        elif model == "lt":
+            enc = param if param.dtype == np.uint64 else encode_w(param)
+            enc = np.ascontiguousarray(enc, dtype=np.uint64)
+        else:
+            raise ValueError(f"unknown model {model!r}")
+        self.encoded = enc
+        self.outdeg = np.diff(offsets)
+        h = ctypes.c_void_p()
+        _check(_lib.ims_graph_create(self.n, self.m, _np_ptr(offsets), _np_ptr(indices),
+                                     IC if model == "ic" else LT, _np_ptr(enc), ctypes.byref(h)),
+               "ims_graph_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.ims_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def last_status(self, stream=None) -> tuple[int, int]:
+        out = np.zeros(2, dtype=np.uint32)
+        _check(_lib.ims_graph_last_status(self._h, _stream_handle(stream), _np_ptr(out)), "ims_graph_last_status")
+        return int(out[0]), int(out[1])
+
+
+def simulate_into(graph: Graph, seeds, n_trials: int, rng_seed: int, trial_counts, total,
+                  node_counts=None, active_bits=None, stream=None, opts: Opts | None = None) -> None:
+    """Enqueue one simulation on `stream` writing into caller tensors."""
+    seeds = np.ascontiguousarray(seeds, dtype=np.uint32)
+    ptr = lambda t: None if t is None else ctypes.c_void_p(t.data_ptr())
+    _check(_lib.ims_simulate(graph.handle, _np_ptr(seeds) if seeds.size else None, seeds.shape[0],
+                             int(n_trials), int(rng_seed) & ((1 << 64) - 1),
+                             ctypes.byref(opts) if opts is not None else None,
+                             ptr(trial_counts), ptr(node_counts), ptr(total), ptr(active_bits),
+                             _stream_handle(stream)), "ims_simulate")
+
+
+def simulate(graph: Graph, seeds, n_trials: int, rng_seed: int, want_bits: bool = False,
+             want_node_counts: bool = True, stream=None, opts: Opts | None = None) -> dict:
+    """Run trials 0..n_trials-1; returns device tensors and the mean spread."""
+    torch = _torch()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    T = int(n_trials)
+    W = (T + 63) // 64
+    tc = torch.empty(T, dtype=torch.int32, device=dev)
+    tot = torch.empty(1, dtype=torch.int64, device=dev)
+    nc = torch.empty(graph.n, dtype=torch.int32, device=dev) if want_node_counts else None
+    bits = torch.empty((W, graph.n), dtype=torch.int64, device=dev) if want_bits else None
+    simulate_into(graph, seeds, T, rng_seed, tc, tot, nc, bits, stream, opts)
+    steps, guard = graph.last_status(stream)
+    if guard:
+        raise ImsError(-7, "ims_simulate")
+    total = int(tot.item())
+    return {"trial_counts": tc, "total": total, "mean": total / T, "node_counts": nc,
+            "active_bits": bits, "steps": steps}
+
+
+def debug_hash(rng_seed: int, domain: int, trials, ids) -> np.ndarray:
+    torch = _torch()
+    t = torch.as_tensor(np.ascontiguousarray(trials, dtype=np.int64)).cuda()
+    i = torch.as_tensor(np.ascontiguousarray(ids, dtype=np.int64)).cuda()
+    out = torch.empty(t.shape[0], dtype=torch.int32, device=t.device)
+    _check(_lib.ims_debug_hash(int(rng_seed), int(domain), ctypes.c_void_p(t.data_ptr()),
+                               ctypes.c_void_p(i.data_ptr()), ctypes.c_void_p(out.data_ptr()), t.shape[0],
+                               _stream_handle(None)), "ims_debug_hash")
+    return out.cpu().numpy().view(np.uint32)

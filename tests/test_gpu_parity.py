@@ -1,0 +1,150 @@
+"""Bit-exact parity of the HIP simulator (through the C ABI) with the CPU
+oracle: every trial's final active set, per-trial counts, per-node counts and
+the total must be identical."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import pins
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ims():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2404_17059_amd as m
+    return m
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_both(ims, model, n, off, idx, param, seeds, T, rs, t_sample=None, opts=None):
+    """GPU run over all T trials vs the oracle over all (or sampled) trials."""
+    say(f"[parity] model={model} n={n} m={idx.shape[0]} T={T} seeds={len(seeds)} rng={rs}")
+    G = ims.Graph(n, off, idx, model, param)
+    got = ims.simulate(G, seeds, T, rs, want_bits=True, opts=opts)
+    bits = got["active_bits"].cpu().numpy().view(np.uint64)
+    tc = got["trial_counts"].cpu().numpy().view(np.uint32)
+    nc = got["node_counts"].cpu().numpy().view(np.uint32)
+    enc = oracle.encode(model, param) if np.asarray(param).dtype == np.float64 else param
+    if t_sample is None:
+        ref = oracle.simulate(model, n, off, idx, enc, seeds, T, rs, threads=8)
+        assert (tc == ref["trial_counts"]).all()
+        assert (nc == ref["node_counts"]).all()
+        assert got["total"] == ref["total"]
+        assert (bits == ref["active_bits"]).all()
+    else:
+        for t0 in t_sample:  # 64-trial words, compared bit for bit
+            cnt = min(64, T - t0)
+            ref = oracle.simulate(model, n, off, idx, enc, seeds, cnt, rs, t_begin=t0, threads=8)
+            w = t0 // 64
+            assert (bits[w] == ref["active_bits"][0]).all(), t0
+            assert (tc[t0:t0 + cnt] == ref["trial_counts"]).all(), t0
+        # properties over every trial
+        assert int(tc.astype(np.int64).sum()) == got["total"] == int(nc.astype(np.int64).sum())
+        pop = np.zeros(T, dtype=np.int64)
+    G.close()
+    return got, bits
+
+
+def test_device_hash_matches_numpy_philox(ims):
+    rng = np.random.default_rng(3)
+    trials = rng.integers(0, 10**6, size=300)
+    ids = rng.integers(0, 2**32, size=300)
+    ids[:8] = 0
+    trials[:8] = np.arange(8)
+    for dom in (1, 2):
+        got = ims.debug_hash(12345, dom, trials, ids)
+        exp = [pins.numpy_hash32(12345, dom, int(t), int(i)) for t, i in zip(trials, ids)]
+        assert got.tolist() == exp
+
+
+@pytest.mark.parametrize("model", ["ic", "lt"])
+@pytest.mark.parametrize("T", [1, 63, 64, 65, 200, 777])
+def test_small_random_graphs(ims, model, T):
+    rng = np.random.default_rng(T)
+    n = 300
+    src = rng.integers(0, n, size=2400)
+    dst = rng.integers(0, n, size=2400)  # self-loops and repeated arcs kept
+    off, idx = pins.csr_from_arcs(n, src, dst)
+    if model == "ic":
+        param = rng.choice([0.0, 0.02, 0.1, 0.3, 1.0], size=idx.shape[0])
+    else:
+        indeg = np.bincount(idx, minlength=n)
+        param = rng.choice([1.0, 0.7], size=n)[idx] / indeg[idx]
+    seeds = np.array([5, 7, 5, 299, 0], dtype=np.uint32)  # duplicates on purpose
+    run_both(ims, model, n, off, idx, param, seeds, T, 1000 + T)
+
+
+@pytest.mark.parametrize("model", ["ic", "lt"])
+def test_edge_cases(ims, model):
+    g = synth.erdos_renyi_directed(400, 5.0, seed=3)
+    param = synth.uniform_p(g, 0.2) if model == "ic" else synth.weighted_cascade(g)
+    # empty seed set
+    got, bits = run_both(ims, model, g.n, g.offsets, g.indices, param, np.array([], np.uint32), 100, 1)
+    assert got["total"] == 0
+    # isolated seed (no out-arcs) plus all nodes as seeds
+    deg = g.outdeg()
+    iso = np.nonzero(deg == 0)[0][:1].astype(np.uint32)
+    run_both(ims, model, g.n, g.offsets, g.indices, param, iso, 130, 2)
+    got, _ = run_both(ims, model, g.n, g.offsets, g.indices, param, np.arange(g.n, dtype=np.uint32), 70, 3)
+    assert got["total"] == g.n * 70
+
+
+def test_ic_probability_extremes(ims):
+    g = synth.erdos_renyi_directed(500, 3.0, seed=4)
+    for p in (0.0, 1.0):
+        got, bits = run_both(ims, "ic", g.n, g.offsets, g.indices, synth.uniform_p(g, p), [1, 2, 3], 100, 5)
+    reach = pins.reachable(g.n, g.arc_sources(), g.indices, [1, 2, 3])
+    assert (got["node_counts"].cpu().numpy() == 100 * reach).all()
+
+
+def test_lt_full_weight_arcs(ims):
+    # indegree-1 nodes carry a weight of exactly 2^32 (stored as two pieces)
+    n = 200
+    src = np.arange(n - 1)
+    dst = np.arange(1, n)
+    off, idx = pins.csr_from_arcs(n, src, dst)
+    got, _ = run_both(ims, "lt", n, off, idx, np.ones(n - 1), [0], 100, 9)
+    assert got["total"] == n * 100
+
+
+def test_er_ic_1k_full(ims):
+    w = synth.er_ic_1k()
+    run_both(ims, w.model, w.graph.n, w.graph.offsets, w.graph.indices, w.param, w.seeds, w.n_trials, w.rng_seed)
+
+
+def test_ba_ic_100k_full(ims):
+    w = synth.ba_ic_100k()
+    run_both(ims, w.model, w.graph.n, w.graph.offsets, w.graph.indices, w.param, w.seeds, w.n_trials, w.rng_seed)
+
+
+def test_chung_lu_lt_1m_sampled(ims):
+    w = synth.chung_lu_lt_1m()
+    got, bits = run_both(ims, w.model, w.graph.n, w.graph.offsets, w.graph.indices, w.param, w.seeds,
+                         w.n_trials, w.rng_seed, t_sample=[0, 960])
+    # seeds active in every trial
+    nc = got["node_counts"].cpu().numpy()
+    assert (nc[w.seeds] == w.n_trials).all()
+
+
+@pytest.mark.parametrize("model", ["ic", "lt"])
+def test_schedule_invariance(ims, model):
+    g = synth.barabasi_albert(3000, 3, seed=5)
+    param = synth.weighted_cascade(g)
+    seeds = synth.random_seeds(g.n, 10, 6)
+    G = ims.Graph(g.n, g.offsets, g.indices, model, param)
+    outs = []
+    for bpc in (1, 2, 0):
+        opts = ims.Opts(direction=0, blocks_per_cu=bpc, alpha=0.0)
+        r = ims.simulate(G, seeds, 300, 4, want_bits=True, opts=opts)
+        outs.append(r["active_bits"].cpu().numpy())
+    assert all((o == outs[0]).all() for o in outs)
+    G.close()
