@@ -93,9 +93,17 @@ int ims_graph_info(const ims_graph* g, int64_t* n, int64_t* m, int* model);
 
 /* Simulation options; NULL = automatic.  Any setting gives the same bits. */
 typedef struct ims_opts {
-    int direction;        /* IC only: 0 = auto, 1 = push only, 2 = pull only */
-    int32_t blocks_per_cu; /* persistent grid occupancy; 0 = auto */
-    double alpha;         /* IC direction switch: pull when frontier arc volume * alpha > unvisited arcs; 0 = default */
+    int shape;             /* 0 = auto, 1 = word-local (one workgroup per 64-trial word runs its
+                              whole cascade), 2 = grid-wide steps (one launch per level / sweep) */
+    int32_t blocks_per_cu; /* workgroups per compute unit; 0 = auto */
+    double alpha;          /* LT grid shape: a sweep marks out-neighbours of joining nodes (and the
+                              next sweep evaluates marked nodes only) when the previous sweep
+                              changed fewer than alpha * W * n (node, word) pairs; 0 = 1/32 */
+    int32_t profile;       /* nonzero: time the simulation kernels with HIP events (see ims_graph_profile) */
+    int32_t test_flags;    /* test hooks, 0 in normal use: bit 0 = LT grid shape without the
+                              threshold prefix table; bit 1 = keep only 1 bit of each threshold
+                              prefix (forces the exact tie path on about half the trials);
+                              bit 2 = LT without the equal-in-weights form */
 } ims_opts;
 
 /* Run trials 0 .. n_trials-1 from one seed set (Section 2).
@@ -106,7 +114,8 @@ typedef struct ims_opts {
  *   node_counts   device uint32[n]: #{t : v in A_t}.                 optional (NULL)
  *   total         device uint64[1]: sum_t |A_t|; sigma = total / T.  required
  *   active_bits   device uint64[ceil(T/64) * n], word-major.         optional (NULL)
- * Asynchronous on `stream`. */
+ * Asynchronous on `stream` in the word-local shape; the grid shape reads one
+ * step counter back per batch of steps and so returns after the run. */
 int ims_simulate(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_t n_trials,
                  uint64_t rng_seed, const ims_opts* opts, uint32_t* trial_counts,
                  uint32_t* node_counts, uint64_t* total, uint64_t* active_bits, void* stream);
@@ -115,6 +124,12 @@ int ims_simulate(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_t
  * or LT sweeps) taken, out[1] = nonzero if the step guard fired.  Waits for
  * `stream`. */
 int ims_graph_last_status(ims_graph* g, void* stream, uint32_t out[2]);
+
+/* Kernel timing of runs made with opts->profile set: waits for the last such
+ * run, then returns the summed duration (ms) of the simulation kernel over the
+ * runs recorded since the last reset (at most 256) and their count; reset != 0
+ * clears the record afterwards. */
+int ims_graph_profile(ims_graph* g, int reset, double* total_ms, uint32_t* count);
 
 /* Test hook: out[i] = H(rng_seed, domain, trials[i], ids[i]) for i < count,
  * computed by the device hash.  Device arrays. */

@@ -34,7 +34,8 @@ _i64, _u64, _u32, _int = ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32, ctype
 
 
 class Opts(ctypes.Structure):
-    _fields_ = [("direction", ctypes.c_int), ("blocks_per_cu", ctypes.c_int32), ("alpha", ctypes.c_double)]
+    _fields_ = [("shape", ctypes.c_int), ("blocks_per_cu", ctypes.c_int32), ("alpha", ctypes.c_double),
+                ("profile", ctypes.c_int32), ("test_flags", ctypes.c_int32)]
 
 
 def _sig(name, res, *args):
@@ -54,6 +55,7 @@ _sig("ims_graph_destroy", _int, _P)
 _sig("ims_graph_info", _int, _P, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_int))
 _sig("ims_simulate", _int, _P, _P, _u32, _u32, _u64, ctypes.POINTER(Opts), _P, _P, _P, _P, _P)
 _sig("ims_graph_last_status", _int, _P, _P, _P)
+_sig("ims_graph_profile", _int, _P, _int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_u32))
 _sig("ims_debug_hash", _int, _u64, _u64, _P, _P, _P, _i64, _P)
 
 
@@ -150,6 +152,13 @@ class Graph:
     @property
     def handle(self):
         return self._h
+
+    def profile(self, reset: bool = True) -> tuple[float, int]:
+        """(summed kernel ms, number of runs) of runs made with Opts.profile."""
+        ms = ctypes.c_double()
+        cnt = ctypes.c_uint32()
+        _check(_lib.ims_graph_profile(self._h, int(reset), ctypes.byref(ms), ctypes.byref(cnt)), "ims_graph_profile")
+        return float(ms.value), int(cnt.value)
 
     def last_status(self, stream=None) -> tuple[int, int]:
         out = np.zeros(2, dtype=np.uint32)

@@ -2,8 +2,9 @@
 //
 // A graph handle holds the device copy of the out-CSR (with IC thresholds), the
 // in-CSR built here for the LT pull sweep, and a workspace that grows with the
-// trial count.  ims_simulate enqueues: clear state -> one cooperative
-// persistent launch (seed init + all levels / sweeps) -> two reductions.
+// trial count.  ims_simulate enqueues: clear state -> either one word-local
+// launch (each workgroup runs whole 64-trial words) or seed init plus one launch
+// per level / sweep in batches -> two reductions.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -79,81 +80,92 @@ struct ims_graph {
     int64_t n = 0, m = 0;
     int model = 0;
     uint64_t total_chunks = 0;  // sum over nodes of ceil(outdeg / kChunk)
+    int cus = 0;
+    std::vector<int64_t> h_off;  // host copy of the out-offsets (launch planning)
     int64_t* d_off = nullptr;
     uint32_t* d_idx = nullptr;
     uint32_t* d_thr = nullptr;
     int64_t* d_in_off = nullptr;
-    uint32_t* d_in_src = nullptr;
-    uint32_t* d_in_w = nullptr;
-    // workspace
-    uint32_t ws_W = 0;
-    uint64_t* d_A = nullptr;
-    uint64_t* d_N[3] = {nullptr, nullptr, nullptr};
-    uint64_t* d_Q[3] = {nullptr, nullptr, nullptr};
+    uint64_t* d_in_arc = nullptr;  // (source | weight piece << 32) per in-arc
+    uint32_t* d_in_src32 = nullptr;  // source per in-arc (uniform-weight form)
+    uint32_t* d_node_w = nullptr;    // common weight piece per node (uniform-weight form)
+    bool lt_uniform = false;
+    // workspace: byte buffers that only grow
+    struct Buf {
+        void* p = nullptr;
+        uint64_t bytes = 0;
+    };
+    Buf A, N[3], Q[3], aux, thp;
+    bool zero_dirty = true;  // N / aux must be zero between runs
     uint32_t* d_qcount = nullptr;
     uint32_t cap = 0;
     uint32_t* d_seeds = nullptr;
+    uint64_t* d_seed_pre = nullptr;  // prefix of seed out-degrees
     uint32_t seeds_cap = 0;
-    uint32_t* d_status = nullptr;
-    bool n_dirty = true;
-    int coop_blocks = 0;
-    int coop_per_cu = 0;
+    uint32_t* d_status = nullptr;     // [0] steps, [1] guard, [2] task counter
+    uint32_t* h_flag = nullptr;       // pinned readback of one step counter
+    uint32_t last_steps = 0;          // hint for the next grid-shape run
+    uint32_t last_shape = 0;
+    // kernel timing ring (ims_graph_profile)
+    static constexpr int kProf = 256;
+    hipEvent_t prof_ev[2 * kProf] = {};
+    uint32_t prof_count = 0;
 
-    void free_workspace()
+    static void release(Buf& b)
     {
-        dev_free(d_A);
-        for (auto& p : d_N) dev_free(p);
-        for (auto& p : d_Q) dev_free(p);
-        ws_W = 0;
+        if (b.p) (void)hipFree(b.p);
+        b.p = nullptr;
+        b.bytes = 0;
     }
     ~ims_graph()
     {
-        free_workspace();
+        for (auto& e : prof_ev)
+            if (e) (void)hipEventDestroy(e);
+        release(A);
+        for (auto& b : N) release(b);
+        for (auto& b : Q) release(b);
+        release(aux);
+        release(thp);
         dev_free(d_off);
         dev_free(d_idx);
         dev_free(d_thr);
         dev_free(d_in_off);
-        dev_free(d_in_src);
-        dev_free(d_in_w);
+        dev_free(d_in_arc);
+        dev_free(d_in_src32);
+        dev_free(d_node_w);
         dev_free(d_qcount);
         dev_free(d_seeds);
+        dev_free(d_seed_pre);
         dev_free(d_status);
+        if (h_flag) (void)hipHostFree(h_flag);
     }
 };
 
 namespace {
 
-int ensure_workspace(ims_graph* g, uint32_t W, hipStream_t s)
+// Device bytes the LT threshold prefix table may take (W * n * 128).
+constexpr uint64_t kThresholdTableBudget = 16ull << 30;
+
+// Grow a workspace buffer to at least `bytes`; a fresh buffer may hold garbage.
+int ensure_buf(ims_graph* g, ims_graph::Buf& b, uint64_t bytes, bool zero_invariant)
 {
-    if (g->ws_W >= W) return IMS_OK;
-    g->free_workspace();
-    const uint64_t cells = (uint64_t)W * (uint64_t)g->n;
-    int rc = dev_alloc(&g->d_A, cells);
+    if (b.bytes >= bytes && b.p) return IMS_OK;
+    ims_graph::release(b);
+    uint8_t* p = nullptr;
+    int rc = dev_alloc(&p, std::max<uint64_t>(bytes, 8));
     if (rc) return rc;
-    if (g->model == IMS_MODEL_IC) {
-        const uint64_t qcap = (uint64_t)W * std::max<uint64_t>(g->total_chunks, 1);
-        for (int i = 0; i < 3; ++i) {
-            if ((rc = dev_alloc(&g->d_N[i], cells))) return rc;
-            if ((rc = dev_alloc(&g->d_Q[i], qcap))) return rc;
-        }
-    }
-    g->ws_W = W;
-    g->n_dirty = true;
-    (void)s;
+    b.p = p;
+    b.bytes = std::max<uint64_t>(bytes, 8);
+    if (zero_invariant) g->zero_dirty = true;
     return IMS_OK;
 }
 
-int coop_grid(ims_graph* g)
+int device_cus(ims_graph* g)
 {
-    if (g->coop_blocks > 0) return IMS_OK;
-    int per_cu = 0;
-    IMS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, imsim::sim_persistent, imsim::kBlock, 0));
+    if (g->cus > 0) return IMS_OK;
     hipDeviceProp_t prop;
     IMS_HIP(hipGetDeviceProperties(&prop, g->device));
-    if (per_cu < 1) return fail(IMS_E_HIP, "sim_persistent cannot be resident (occupancy 0)");
-    if (!prop.cooperativeLaunch) return fail(IMS_E_UNSUPPORTED, "device lacks cooperative launch");
-    g->coop_per_cu = per_cu;
-    g->coop_blocks = per_cu * prop.multiProcessorCount;
+    g->cus = prop.multiProcessorCount;
     return IMS_OK;
 }
 
@@ -223,7 +235,7 @@ int ims_graph_create(int64_t n, int64_t m, const int64_t* offsets, const uint32_
     // 2^32 is stored as two pieces of 2^31 so every piece fits 32 bits, and
     // zero weights are dropped (they never add to a sum).
     std::vector<int64_t> in_off;
-    std::vector<uint32_t> in_src, in_w;
+    std::vector<uint64_t> in_arc;
     if (model == IMS_MODEL_LT) {
         const uint64_t* w64 = (const uint64_t*)param;
         std::vector<uint64_t> wsum((size_t)std::max<int64_t>(n, 1), 0);
@@ -239,8 +251,7 @@ int ims_graph_create(int64_t n, int64_t m, const int64_t* offsets, const uint32_
         in_off.assign((size_t)n + 1, 0);
         for (int64_t v = 0; v < n; ++v) in_off[v + 1] = in_off[v] + cnt[v + 1];
         const int64_t mi = in_off[n];
-        in_src.resize((size_t)std::max<int64_t>(mi, 1));
-        in_w.resize((size_t)std::max<int64_t>(mi, 1));
+        in_arc.resize((size_t)std::max<int64_t>(mi, 1));
         std::vector<int64_t> pos(in_off.begin(), in_off.end() - 1);
         for (int64_t u = 0; u < n; ++u)
             for (int64_t e = offsets[u]; e < offsets[u + 1]; ++e) {
@@ -248,13 +259,10 @@ int ims_graph_create(int64_t n, int64_t m, const int64_t* offsets, const uint32_
                 if (w == 0) continue;
                 const uint32_t v = indices[e];
                 if (w == (1ull << 32)) {
-                    in_src[pos[v]] = (uint32_t)u;
-                    in_w[pos[v]++] = 1u << 31;
-                    in_src[pos[v]] = (uint32_t)u;
-                    in_w[pos[v]++] = 1u << 31;
+                    in_arc[pos[v]++] = (uint64_t)u | ((uint64_t)(1u << 31) << 32);
+                    in_arc[pos[v]++] = (uint64_t)u | ((uint64_t)(1u << 31) << 32);
                 } else {
-                    in_src[pos[v]] = (uint32_t)u;
-                    in_w[pos[v]++] = (uint32_t)w;
+                    in_arc[pos[v]++] = (uint64_t)u | (w << 32);
                 }
             }
     }
@@ -266,6 +274,7 @@ int ims_graph_create(int64_t n, int64_t m, const int64_t* offsets, const uint32_
     g->m = m;
     g->model = model;
     g->total_chunks = chunks;
+    g->h_off.assign(offsets, offsets + n + 1);
     auto bail = [&](int code) {
         delete g;
         return code;
@@ -282,16 +291,32 @@ int ims_graph_create(int64_t n, int64_t m, const int64_t* offsets, const uint32_
     } else {
         const int64_t mi = in_off[n];
         if ((rc = dev_alloc(&g->d_in_off, (uint64_t)n + 1))) return bail(rc);
-        if ((rc = dev_alloc(&g->d_in_src, (uint64_t)mi))) return bail(rc);
-        if ((rc = dev_alloc(&g->d_in_w, (uint64_t)mi))) return bail(rc);
+        if ((rc = dev_alloc(&g->d_in_arc, (uint64_t)mi))) return bail(rc);
+        // uniform-weight form: every node's pieces equal
+        std::vector<uint32_t> node_w((size_t)std::max<int64_t>(n, 1), 0), src32((size_t)std::max<int64_t>(mi, 1), 0);
+        bool uniform = true;
+        for (int64_t v = 0; v < n && uniform; ++v)
+            for (int64_t k = in_off[v]; k < in_off[v + 1]; ++k) {
+                const uint32_t piece = (uint32_t)(in_arc[k] >> 32);
+                if (k == in_off[v]) node_w[v] = piece;
+                else if (piece != node_w[v]) { uniform = false; break; }
+            }
+        g->lt_uniform = uniform;
+        if (uniform) {
+            for (int64_t k = 0; k < mi; ++k) src32[k] = (uint32_t)in_arc[k];
+            if ((rc = dev_alloc(&g->d_in_src32, (uint64_t)mi))) return bail(rc);
+            if ((rc = dev_alloc(&g->d_node_w, (uint64_t)n))) return bail(rc);
+            if ((mi > 0 && hipMemcpy(g->d_in_src32, src32.data(), sizeof(uint32_t) * mi, hipMemcpyHostToDevice) != hipSuccess) ||
+                (n > 0 && hipMemcpy(g->d_node_w, node_w.data(), sizeof(uint32_t) * n, hipMemcpyHostToDevice) != hipSuccess))
+                return bail(fail(IMS_E_HIP, "in-CSR upload failed"));
+        }
         if (hipMemcpy(g->d_in_off, in_off.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice) != hipSuccess ||
-            (mi > 0 && hipMemcpy(g->d_in_src, in_src.data(), sizeof(uint32_t) * mi, hipMemcpyHostToDevice) != hipSuccess) ||
-            (mi > 0 && hipMemcpy(g->d_in_w, in_w.data(), sizeof(uint32_t) * mi, hipMemcpyHostToDevice) != hipSuccess))
+            (mi > 0 && hipMemcpy(g->d_in_arc, in_arc.data(), sizeof(uint64_t) * mi, hipMemcpyHostToDevice) != hipSuccess))
             return bail(fail(IMS_E_HIP, "in-CSR upload failed"));
     }
     g->cap = (uint32_t)std::min<int64_t>(n + 8, 0xFFFFFFF0ll);
     if ((rc = dev_alloc(&g->d_qcount, g->cap))) return bail(rc);
-    if ((rc = dev_alloc(&g->d_status, 2))) return bail(rc);
+    if ((rc = dev_alloc(&g->d_status, 4))) return bail(rc);
     *out = g;
     return IMS_OK;
 }
@@ -324,6 +349,8 @@ int ims_simulate(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_t
     if (!trial_counts || !total) return fail(IMS_E_INVALID_ARG, "ims_simulate: trial_counts and total are required");
     if (n_seeds > 0 && !seeds) return fail(IMS_E_INVALID_ARG, "ims_simulate: seeds is NULL");
     hipStream_t s = (hipStream_t)stream;
+    int rc = device_cus(g);
+    if (rc) return rc;
 
     // seeds: range check and set semantics on the host
     std::vector<uint32_t> sv(seeds, seeds + n_seeds);
@@ -333,25 +360,61 @@ int ims_simulate(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_t
     sv.erase(std::unique(sv.begin(), sv.end()), sv.end());
 
     const uint32_t W = (n_trials + 63) / 64;
-    int rc = ensure_workspace(g, W, s);
-    if (rc) return rc;
-    if ((rc = coop_grid(g))) return rc;
-    if (g->seeds_cap < sv.size()) {
+    const uint64_t n = (uint64_t)g->n;
+    const uint64_t cells = (uint64_t)W * n;
+    // execution shape: word-local when there are enough words to occupy the
+    // device or the graph is small; grid-wide steps otherwise
+    int shape = opts ? opts->shape : 0;
+    if (shape == 0) shape = (W >= (uint32_t)g->cus / 4 || n <= 65536) ? 1 : 2;
+    if (shape != 1 && shape != 2) return fail(IMS_E_INVALID_ARG, "ims_simulate: unknown shape %d", shape);
+
+    if (!active_bits && (rc = ensure_buf(g, g->A, cells * 8, false))) return rc;
+    if (shape == 1) {
+        if (g->model == IMS_MODEL_IC) {
+            if ((rc = ensure_buf(g, g->N[0], cells * 8, true))) return rc;
+            if ((rc = ensure_buf(g, g->Q[0], cells * 4, false))) return rc;
+            if ((rc = ensure_buf(g, g->Q[1], cells * 4, false))) return rc;
+            if ((rc = ensure_buf(g, g->Q[2], cells * 16, false))) return rc;
+        } else {
+            if ((rc = ensure_buf(g, g->aux, cells * 4, true))) return rc;
+            for (int i = 0; i < 3; ++i)
+                if ((rc = ensure_buf(g, g->Q[i], cells * 4, false))) return rc;
+        }
+    } else if (g->model == IMS_MODEL_IC) {
+        const uint64_t qcap = (uint64_t)W * std::max<uint64_t>(g->total_chunks, 1);
+        for (int i = 0; i < 3; ++i) {
+            if ((rc = ensure_buf(g, g->N[i], cells * 8, true))) return rc;
+            if ((rc = ensure_buf(g, g->Q[i], qcap * 8, false))) return rc;
+        }
+    } else {
+        if ((rc = ensure_buf(g, g->aux, cells * 4, true))) return rc;
+    }
+    // LT grid shape: threshold prefix table when it fits the budget
+    const int test_flags = opts ? opts->test_flags : 0;
+    const bool use_table = shape == 2 && g->model == IMS_MODEL_LT && cells * 128 <= kThresholdTableBudget && !(test_flags & 1);
+    if (use_table && (rc = ensure_buf(g, g->thp, cells * 128, false))) return rc;
+    if (g->seeds_cap < sv.size() || !g->d_seeds) {
         dev_free(g->d_seeds);
+        dev_free(g->d_seed_pre);
         if ((rc = dev_alloc(&g->d_seeds, sv.size()))) return rc;
+        if ((rc = dev_alloc(&g->d_seed_pre, sv.size() + 1))) return rc;
         g->seeds_cap = (uint32_t)sv.size();
     }
+    std::vector<uint64_t> seed_pre(sv.size() + 1, 0);
+    for (size_t i = 0; i < sv.size(); ++i) seed_pre[i + 1] = seed_pre[i] + (uint64_t)(g->h_off[sv[i] + 1] - g->h_off[sv[i]]);
+    if (!g->h_flag) IMS_HIP(hipHostMalloc((void**)&g->h_flag, 4 * sizeof(uint32_t), hipHostMallocDefault));
     if (!sv.empty()) IMS_HIP(hipMemcpyAsync(g->d_seeds, sv.data(), sv.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    IMS_HIP(hipMemcpyAsync(g->d_seed_pre, seed_pre.data(), seed_pre.size() * sizeof(uint64_t), hipMemcpyHostToDevice, s));
 
-    const uint64_t cells = (uint64_t)W * (uint64_t)g->n;
-    uint64_t* A = active_bits ? active_bits : g->d_A;
+    uint64_t* A = active_bits ? active_bits : (uint64_t*)g->A.p;
     if ((rc = fill_async<uint64_t>(A, cells, 0ull, s))) return rc;
-    if (g->model == IMS_MODEL_IC && g->n_dirty) {
-        for (int i = 0; i < 3; ++i)
-            if ((rc = fill_async<uint64_t>(g->d_N[i], cells, 0ull, s))) return rc;
-        g->n_dirty = false;
+    if (g->zero_dirty) {
+        for (auto& b : g->N)
+            if (b.p && (rc = fill_async<uint8_t>((uint8_t*)b.p, b.bytes, 0, s))) return rc;
+        if (g->aux.p && (rc = fill_async<uint8_t>((uint8_t*)g->aux.p, g->aux.bytes, 0, s))) return rc;
+        g->zero_dirty = false;
     }
-    if ((rc = fill_async<uint32_t>(g->d_qcount, g->cap, 0u, s))) return rc;
+    if ((rc = fill_async<uint32_t>(g->d_status, 4, 0u, s))) return rc;
     if ((rc = fill_async<uint32_t>(trial_counts, n_trials, 0u, s))) return rc;
     if ((rc = fill_async<unsigned long long>((unsigned long long*)total, 1, 0ull, s))) return rc;
 
@@ -360,36 +423,109 @@ int ims_simulate(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_t
     P.T = n_trials;
     P.W = W;
     P.seed = rng_seed;
-    P.model = g->model;
-    P.cap = g->cap;
     P.off = g->d_off;
     P.idx = g->d_idx;
     P.thr = g->d_thr;
     P.in_off = g->d_in_off;
-    P.in_src = g->d_in_src;
-    P.in_w = g->d_in_w;
+    P.in_arc = g->d_in_arc;
+    P.in_src32 = g->d_in_src32;
+    P.node_w = g->d_node_w;
+    P.lt_uniform = g->lt_uniform && !(test_flags & 4) ? 1 : 0;
+    P.thp = nullptr;
+    P.thp_shift = (test_flags & 2) ? 31u : 16u;
     P.A = A;
-    P.N0 = g->d_N[0];
-    P.N1 = g->d_N[1];
-    P.N2 = g->d_N[2];
-    P.Q0 = g->d_Q[0];
-    P.Q1 = g->d_Q[1];
-    P.Q2 = g->d_Q[2];
+    for (int i = 0; i < 3; ++i) {
+        P.N[i] = (uint64_t*)g->N[i].p;
+        P.Q[i] = (uint64_t*)g->Q[i].p;
+    }
     P.qcount = g->d_qcount;
+    P.aux = (uint32_t*)g->aux.p;
     P.seeds = g->d_seeds;
     P.n_seeds = (uint32_t)sv.size();
+    P.task_counter = g->d_status + 2;
     P.status = g->d_status;
+    P.cap = g->cap;
 
-    int blocks = g->coop_blocks;
-    if (opts && opts->blocks_per_cu > 0) {
-        const int cus = g->coop_blocks / g->coop_per_cu;
-        blocks = std::min(opts->blocks_per_cu, g->coop_per_cu) * cus;
+    const bool prof = opts && opts->profile && g->prof_count < ims_graph::kProf;
+    const uint32_t slot = g->prof_count;
+    if (prof) {
+        for (int k = 0; k < 2; ++k)
+            if (!g->prof_ev[2 * slot + k]) IMS_HIP(hipEventCreate(&g->prof_ev[2 * slot + k]));
+        IMS_HIP(hipEventRecord(g->prof_ev[2 * slot], s));
     }
-    void* args[] = {&P};
-    IMS_HIP(hipLaunchCooperativeKernel((const void*)imsim::sim_persistent, dim3(blocks), dim3(imsim::kBlock), args, 0, s));
+    if (shape == 1) {
+        const int per_cu = opts && opts->blocks_per_cu > 0 ? opts->blocks_per_cu : 2;
+        const uint32_t blocks = std::min<uint32_t>(W, (uint32_t)(g->cus * per_cu));
+        if (g->model == IMS_MODEL_IC)
+            hipLaunchKernelGGL(imsim::word_ic_kernel, dim3(blocks), dim3(imsim::kBlock), 0, s, P, n);
+        else
+            hipLaunchKernelGGL(imsim::word_lt_kernel, dim3(blocks), dim3(imsim::kBlock), 0, s, P, n);
+        IMS_HIP(hipGetLastError());
+    } else {
+        const int per_cu = opts && opts->blocks_per_cu > 0 ? opts->blocks_per_cu : 8;
+        const uint32_t blocks = (uint32_t)(g->cus * per_cu);
+        if ((rc = fill_async<uint32_t>(g->d_qcount, g->cap, 0u, s))) return rc;
+        hipLaunchKernelGGL(imsim::grid_seed_kernel, dim3(std::max<uint32_t>(1, std::min<uint32_t>(blocks, (P.n_seeds * W + 255) / 256))),
+                           dim3(imsim::kBlock), 0, s, P, g->model);
+        IMS_HIP(hipGetLastError());
+        // LT sweep marks (aux) start cleared every run
+        const uint32_t tau = opts && opts->alpha > 0.0 ? (uint32_t)std::min<double>(opts->alpha * (double)cells, 4e9)
+                                                       : (uint32_t)std::min<uint64_t>(cells / 32 + 1, 0xFFFFFFFFull);
+        if (g->model == IMS_MODEL_LT) {
+            if (use_table) {
+                P.thp = (const uint16_t*)g->thp.p;
+                hipLaunchKernelGGL(imsim::lt_threshold_table_kernel, dim3(blocks), dim3(imsim::kBlock), 0, s, P, (uint16_t*)g->thp.p);
+                IMS_HIP(hipGetLastError());
+            }
+            if ((rc = fill_async<uint32_t>((uint32_t*)g->aux.p, cells, 0u, s))) return rc;
+            const uint64_t seed_arcs = seed_pre.back();
+            hipLaunchKernelGGL(imsim::grid_lt_seed_mark_kernel,
+                               dim3((uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(blocks, (seed_arcs + imsim::kBlock - 1) / imsim::kBlock))),
+                               dim3(imsim::kBlock), 0, s, P, (const uint64_t*)g->d_seed_pre);
+            IMS_HIP(hipGetLastError());
+        }
+        // steps in batches; a step after the last productive one returns at
+        // once, so only the end of each batch is read back
+        uint32_t next = 0, batch = std::max<uint32_t>(8, g->last_steps + 2);
+        bool done = false;
+        while (!done) {
+            const uint32_t end = std::min<uint32_t>(next + batch, g->cap);
+            for (uint32_t st = next; st < end; ++st) {
+                if (g->model == IMS_MODEL_IC)
+                    hipLaunchKernelGGL(imsim::grid_ic_level_kernel, dim3(blocks), dim3(imsim::kBlock), 0, s, P, st);
+                else
+                    hipLaunchKernelGGL(imsim::grid_lt_sweep_kernel, dim3(blocks), dim3(imsim::kBlock), 0, s, P, st, tau);
+            }
+            IMS_HIP(hipGetLastError());
+            // IC: level `end` has no items; LT: sweep end-1 changed nothing
+            const uint32_t probe = g->model == IMS_MODEL_IC ? std::min(end, g->cap - 1) : end - 1;
+            IMS_HIP(hipMemcpyAsync(g->h_flag, g->d_qcount + probe, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+            IMS_HIP(hipStreamSynchronize(s));
+            done = g->h_flag[0] == 0 || end >= g->cap;
+            next = end;
+        }
+        // number of steps: first step counter that is zero
+        std::vector<uint32_t> qc(std::min<uint32_t>(next + 1, g->cap));
+        IMS_HIP(hipMemcpy(qc.data(), g->d_qcount, qc.size() * sizeof(uint32_t), hipMemcpyDeviceToHost));
+        uint32_t steps = 0;
+        while (steps < next && qc[steps] != 0) ++steps;
+        if (g->model == IMS_MODEL_LT) steps += 1;
+        g->last_steps = steps;
+        if (next >= g->cap && qc.back() != 0) {
+            uint32_t one = 1;
+            IMS_HIP(hipMemcpyAsync(g->d_status + 1, &one, sizeof one, hipMemcpyHostToDevice, s));
+        }
+        IMS_HIP(hipMemcpyAsync(g->d_status, &steps, sizeof steps, hipMemcpyHostToDevice, s));
+        IMS_HIP(hipStreamSynchronize(s));
+    }
+    if (prof) {
+        IMS_HIP(hipEventRecord(g->prof_ev[2 * slot + 1], s));
+        g->prof_count = slot + 1;
+    }
+    g->last_shape = (uint32_t)shape;
 
-    if (g->n > 0) {
-        const uint64_t nblk = std::min<uint64_t>(((uint64_t)g->n + imsim::kBlock - 1) / imsim::kBlock, 1024);
+    if (n > 0) {
+        const uint64_t nblk = std::min<uint64_t>((n + imsim::kBlock - 1) / imsim::kBlock, 1024);
         hipLaunchKernelGGL(imsim::reduce_trial_counts, dim3((unsigned)nblk, W), dim3(imsim::kBlock), 0, s, A, g->n, n_trials,
                            trial_counts);
         IMS_HIP(hipGetLastError());
@@ -405,7 +541,23 @@ int ims_graph_last_status(ims_graph* g, void* stream, uint32_t out[2])
     if (!g || !out) return fail(IMS_E_INVALID_ARG, "ims_graph_last_status: bad arguments");
     IMS_HIP(hipMemcpyAsync(out, g->d_status, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, (hipStream_t)stream));
     IMS_HIP(hipStreamSynchronize((hipStream_t)stream));
-    if (out[1]) g->n_dirty = true;
+    if (out[1]) g->zero_dirty = true;
+    return IMS_OK;
+}
+
+int ims_graph_profile(ims_graph* g, int reset, double* total_ms, uint32_t* count)
+{
+    if (!g || !total_ms || !count) return fail(IMS_E_INVALID_ARG, "ims_graph_profile: bad arguments");
+    double sum = 0.0;
+    for (uint32_t i = 0; i < g->prof_count; ++i) {
+        IMS_HIP(hipEventSynchronize(g->prof_ev[2 * i + 1]));
+        float ms = 0.f;
+        IMS_HIP(hipEventElapsedTime(&ms, g->prof_ev[2 * i], g->prof_ev[2 * i + 1]));
+        sum += ms;
+    }
+    *total_ms = sum;
+    *count = g->prof_count;
+    if (reset) g->prof_count = 0;
     return IMS_OK;
 }
 

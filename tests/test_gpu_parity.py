@@ -137,14 +137,50 @@ def test_chung_lu_lt_1m_sampled(ims):
 
 @pytest.mark.parametrize("model", ["ic", "lt"])
 def test_schedule_invariance(ims, model):
+    """Word-local and grid-wide shapes, several occupancies: identical bits,
+    equal to the oracle."""
     g = synth.barabasi_albert(3000, 3, seed=5)
     param = synth.weighted_cascade(g)
     seeds = synth.random_seeds(g.n, 10, 6)
     G = ims.Graph(g.n, g.offsets, g.indices, model, param)
     outs = []
-    for bpc in (1, 2, 0):
-        opts = ims.Opts(direction=0, blocks_per_cu=bpc, alpha=0.0)
-        r = ims.simulate(G, seeds, 300, 4, want_bits=True, opts=opts)
-        outs.append(r["active_bits"].cpu().numpy())
+    for shape in (1, 2):
+        for bpc in (1, 3, 0):
+            say(f"[parity] schedule model={model} shape={shape} bpc={bpc}")
+            opts = ims.Opts(shape=shape, blocks_per_cu=bpc, alpha=0.0, profile=0)
+            r = ims.simulate(G, seeds, 300, 4, want_bits=True, opts=opts)
+            outs.append(r["active_bits"].cpu().numpy())
     assert all((o == outs[0]).all() for o in outs)
+    ref = oracle.simulate(model, g.n, g.offsets, g.indices, oracle.encode(model, param), seeds, 300, 4)
+    assert (outs[0].view(np.uint64) == ref["active_bits"]).all()
     G.close()
+
+
+@pytest.mark.parametrize("model", ["ic", "lt"])
+@pytest.mark.parametrize("shape", [1, 2])
+def test_both_shapes_on_random_graphs(ims, model, shape):
+    rng = np.random.default_rng(40 + shape)
+    n = 2000
+    src = rng.integers(0, n, size=12000)
+    dst = rng.integers(0, n, size=12000)
+    off, idx = pins.csr_from_arcs(n, src, dst)
+    if model == "ic":
+        param = rng.choice([0.0, 0.05, 0.2, 1.0], size=idx.shape[0])
+    else:
+        indeg = np.bincount(idx, minlength=n)
+        param = 1.0 / indeg[idx]
+    opts = ims.Opts(shape=shape, blocks_per_cu=0, alpha=0.0, profile=0)
+    run_both(ims, model, n, off, idx, param, np.array([3, 9, 27], np.uint32), 333, 17, opts=opts)
+
+
+@pytest.mark.parametrize("flags,alpha", [(0, 0.0), (1, 0.0), (2, 0.0), (2, 1.0), (0, 1e-9), (4, 0.0), (6, 0.0), (5, 1.0)])
+def test_lt_grid_threshold_paths_and_direction_switch(ims, flags, alpha):
+    """LT grid shape with the threshold prefix table, without it, with 1-bit
+    prefixes (exact tie path on about half the trials), with and without the
+    equal-in-weights counting form, and with the marking direction always on
+    (alpha=1) or always off (alpha tiny): identical bits."""
+    g = synth.chung_lu_directed(20000, 2.1, 8.0, seed=31)
+    param = synth.weighted_cascade(g)
+    seeds = synth.top_outdeg_seeds(g, 20)
+    opts = ims.Opts(shape=2, blocks_per_cu=0, alpha=alpha, profile=0, test_flags=flags)
+    run_both(ims, "lt", g.n, g.offsets, g.indices, param, seeds, 200, 23, opts=opts)
