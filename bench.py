@@ -83,6 +83,20 @@ def cpu_baseline(w, sample_trials: int, threads: int) -> dict:
             "trials_per_sec": sample_trials / dt, "seconds": round(dt, 3)}
 
 
+def copy_calibration(mib: int) -> int:
+    """A plain copy of known size: reads and writes mib MiB each time, so
+    hardware byte counters can be scaled to bytes."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_mib": mib, "bytes_read_per_copy": n * 4, "bytes_written_per_copy": n * 4}))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,7 +104,11 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="lt_chunglu_1m", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-sample", type=int, default=64, help="oracle trials timed for cpu_baseline (0 = skip)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a device-to-device copy of MIB MiB three times (HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        return copy_calibration(args.copy_calibration)
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported by this build "
               "(trials would shard across GPUs with one all-reduce of the counts at the end).", file=sys.stderr)
@@ -116,7 +134,7 @@ def main() -> int:
     tc = torch.empty(T, dtype=torch.int32, device=dev)
     tot = torch.empty(1, dtype=torch.int64, device=dev)
     nc = torch.empty(g.n, dtype=torch.int32, device=dev)
-    opts = ims.Opts(direction=0, blocks_per_cu=0, alpha=0.0, profile=1)
+    opts = ims.Opts(shape=0, blocks_per_cu=0, alpha=0.0, profile=1)
     stream = torch.cuda.current_stream()
 
     for i in range(args.warmup):

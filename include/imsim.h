@@ -100,10 +100,10 @@ typedef struct ims_opts {
                               next sweep evaluates marked nodes only) when the previous sweep
                               changed fewer than alpha * W * n (node, word) pairs; 0 = 1/32 */
     int32_t profile;       /* nonzero: time the simulation kernels with HIP events (see ims_graph_profile) */
-    int32_t test_flags;    /* test hooks, 0 in normal use: bit 0 = LT grid shape without the
-                              threshold prefix table; bit 1 = keep only 1 bit of each threshold
-                              prefix (forces the exact tie path on about half the trials);
-                              bit 2 = LT without the equal-in-weights form */
+    int32_t test_flags;    /* test hooks, 0 in normal use: bit 0 = LT grid shape without a
+                              threshold table (hashes drawn in the kernel); bit 1 = unused;
+                              bit 2 = LT without the equal-in-weights form; bit 3 = LT grid
+                              shape with full threshold hashes instead of count thresholds */
 } ims_opts;
 
 /* Run trials 0 .. n_trials-1 from one seed set (Section 2).

@@ -90,12 +90,14 @@ struct ims_graph {
     uint32_t* d_in_src32 = nullptr;  // source per in-arc (uniform-weight form)
     uint32_t* d_node_w = nullptr;    // common weight piece per node (uniform-weight form)
     bool lt_uniform = false;
+    uint32_t* d_bfirst = nullptr;    // LT grid shape: first node of each batch
+    uint32_t nbatch = 0;
     // workspace: byte buffers that only grow
     struct Buf {
         void* p = nullptr;
         uint64_t bytes = 0;
     };
-    Buf A, N[3], Q[3], aux, thp;
+    Buf A, N[3], Q[3], aux, thp, Anm;
     bool zero_dirty = true;  // N / aux must be zero between runs
     uint32_t* d_qcount = nullptr;
     uint32_t cap = 0;
@@ -126,6 +128,7 @@ struct ims_graph {
         for (auto& b : Q) release(b);
         release(aux);
         release(thp);
+        release(Anm);
         dev_free(d_off);
         dev_free(d_idx);
         dev_free(d_thr);
@@ -133,6 +136,7 @@ struct ims_graph {
         dev_free(d_in_arc);
         dev_free(d_in_src32);
         dev_free(d_node_w);
+        dev_free(d_bfirst);
         dev_free(d_qcount);
         dev_free(d_seeds);
         dev_free(d_seed_pre);
@@ -143,8 +147,8 @@ struct ims_graph {
 
 namespace {
 
-// Device bytes the LT threshold prefix table may take (W * n * 128).
-constexpr uint64_t kThresholdTableBudget = 16ull << 30;
+// Device bytes the LT threshold table may take (W * n * 256).
+constexpr uint64_t kThresholdTableBudget = 32ull << 30;
 
 // Grow a workspace buffer to at least `bytes`; a fresh buffer may hold garbage.
 int ensure_buf(ims_graph* g, ims_graph::Buf& b, uint64_t bytes, bool zero_invariant)
@@ -313,6 +317,31 @@ int ims_graph_create(int64_t n, int64_t m, const int64_t* offsets, const uint32_
         if (hipMemcpy(g->d_in_off, in_off.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice) != hipSuccess ||
             (mi > 0 && hipMemcpy(g->d_in_arc, in_arc.data(), sizeof(uint64_t) * mi, hipMemcpyHostToDevice) != hipSuccess))
             return bail(fail(IMS_E_HIP, "in-CSR upload failed"));
+        // node batches for the grid-shape sweep: at most 8 consecutive nodes
+        // whose in-arcs fit one 64-arc chunk; a node with more arcs is alone
+        std::vector<uint32_t> bfirst(1, 0);
+        uint32_t bcnt = 0;
+        uint64_t barcs = 0;
+        for (int64_t v = 0; v < n; ++v) {
+            const uint64_t d = (uint64_t)(in_off[v + 1] - in_off[v]);
+            if (bcnt > 0 && (bcnt == 8 || barcs + d > 64)) {
+                bfirst.push_back((uint32_t)v);
+                bcnt = 0;
+                barcs = 0;
+            }
+            ++bcnt;
+            barcs += d;
+            if (d > 64) {
+                bfirst.push_back((uint32_t)(v + 1));
+                bcnt = 0;
+                barcs = 0;
+            }
+        }
+        if (bcnt > 0) bfirst.push_back((uint32_t)n);
+        g->nbatch = (uint32_t)(bfirst.size() - 1);
+        if ((rc = dev_alloc(&g->d_bfirst, bfirst.size()))) return bail(rc);
+        if (hipMemcpy(g->d_bfirst, bfirst.data(), sizeof(uint32_t) * bfirst.size(), hipMemcpyHostToDevice) != hipSuccess)
+            return bail(fail(IMS_E_HIP, "batch upload failed"));
     }
     g->cap = (uint32_t)std::min<int64_t>(n + 8, 0xFFFFFFF0ll);
     if ((rc = dev_alloc(&g->d_qcount, g->cap))) return bail(rc);
@@ -388,11 +417,19 @@ int ims_simulate(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_t
         }
     } else {
         if ((rc = ensure_buf(g, g->aux, cells * 4, true))) return rc;
+        if ((rc = ensure_buf(g, g->Anm, cells * 8, false))) return rc;
     }
     // LT grid shape: threshold prefix table when it fits the budget
     const int test_flags = opts ? opts->test_flags : 0;
-    const bool use_table = shape == 2 && g->model == IMS_MODEL_LT && cells * 128 <= kThresholdTableBudget && !(test_flags & 1);
-    if (use_table && (rc = ensure_buf(g, g->thp, cells * 128, false))) return rc;
+    // LT grid shape threshold form: count thresholds (equal in-weights, 64 B
+    // per node-word), full hashes (256 B), or hashes drawn in the kernel
+    int lt_mode = 0;
+    if (shape == 2 && g->model == IMS_MODEL_LT && !(test_flags & 1)) {
+        if (g->lt_uniform && !(test_flags & 4) && cells * 64 <= kThresholdTableBudget && !(test_flags & 8)) lt_mode = 2;
+        else if (cells * 256 <= kThresholdTableBudget) lt_mode = 1;
+    }
+    const bool use_table = lt_mode != 0;
+    if (use_table && (rc = ensure_buf(g, g->thp, cells * (lt_mode == 2 ? 64 : 256), false))) return rc;
     if (g->seeds_cap < sv.size() || !g->d_seeds) {
         dev_free(g->d_seeds);
         dev_free(g->d_seed_pre);
@@ -432,8 +469,13 @@ int ims_simulate(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_t
     P.node_w = g->d_node_w;
     P.lt_uniform = g->lt_uniform && !(test_flags & 4) ? 1 : 0;
     P.thp = nullptr;
+    P.th32 = nullptr;
+    P.kmin = nullptr;
     P.thp_shift = (test_flags & 2) ? 31u : 16u;
     P.A = A;
+    P.Anm = (uint64_t*)g->Anm.p;
+    P.bfirst = g->d_bfirst;
+    P.nbatch = g->nbatch;
     for (int i = 0; i < 3; ++i) {
         P.N[i] = (uint64_t*)g->N[i].p;
         P.Q[i] = (uint64_t*)g->Q[i].p;
@@ -442,6 +484,7 @@ int ims_simulate(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_t
     P.aux = (uint32_t*)g->aux.p;
     P.seeds = g->d_seeds;
     P.n_seeds = (uint32_t)sv.size();
+    P.seed_arcs = seed_pre.back();
     P.task_counter = g->d_status + 2;
     P.status = g->d_status;
     P.cap = g->cap;
@@ -465,22 +508,28 @@ int ims_simulate(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_t
         const int per_cu = opts && opts->blocks_per_cu > 0 ? opts->blocks_per_cu : 8;
         const uint32_t blocks = (uint32_t)(g->cus * per_cu);
         if ((rc = fill_async<uint32_t>(g->d_qcount, g->cap, 0u, s))) return rc;
-        hipLaunchKernelGGL(imsim::grid_seed_kernel, dim3(std::max<uint32_t>(1, std::min<uint32_t>(blocks, (P.n_seeds * W + 255) / 256))),
-                           dim3(imsim::kBlock), 0, s, P, g->model);
-        IMS_HIP(hipGetLastError());
-        // LT sweep marks (aux) start cleared every run
         const uint32_t tau = opts && opts->alpha > 0.0 ? (uint32_t)std::min<double>(opts->alpha * (double)cells, 4e9)
                                                        : (uint32_t)std::min<uint64_t>(cells / 32 + 1, 0xFFFFFFFFull);
-        if (g->model == IMS_MODEL_LT) {
-            if (use_table) {
-                P.thp = (const uint16_t*)g->thp.p;
-                hipLaunchKernelGGL(imsim::lt_threshold_table_kernel, dim3(blocks), dim3(imsim::kBlock), 0, s, P, (uint16_t*)g->thp.p);
+        if (g->model == IMS_MODEL_IC) {
+            hipLaunchKernelGGL(imsim::grid_seed_kernel, dim3(std::max<uint32_t>(1, std::min<uint32_t>(blocks, (P.n_seeds * W + 255) / 256))),
+                               dim3(imsim::kBlock), 0, s, P, g->model);
+            IMS_HIP(hipGetLastError());
+        } else {
+            // node-major state and sweep marks start cleared every run
+            if ((rc = fill_async<uint64_t>(P.Anm, cells, 0ull, s))) return rc;
+            if ((rc = fill_async<uint32_t>((uint32_t*)g->aux.p, cells, 0u, s))) return rc;
+            if (lt_mode == 1) {
+                P.th32 = (const uint32_t*)g->thp.p;
+                hipLaunchKernelGGL(imsim::ltg_table_kernel, dim3(blocks), dim3(imsim::kBlock), 0, s, P, (uint32_t*)g->thp.p);
+                IMS_HIP(hipGetLastError());
+            } else if (lt_mode == 2) {
+                P.kmin = (const uint8_t*)g->thp.p;
+                hipLaunchKernelGGL(imsim::ltg_kmin_kernel, dim3(blocks), dim3(imsim::kBlock), 0, s, P, (uint8_t*)g->thp.p);
                 IMS_HIP(hipGetLastError());
             }
-            if ((rc = fill_async<uint32_t>((uint32_t*)g->aux.p, cells, 0u, s))) return rc;
-            const uint64_t seed_arcs = seed_pre.back();
-            hipLaunchKernelGGL(imsim::grid_lt_seed_mark_kernel,
-                               dim3((uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(blocks, (seed_arcs + imsim::kBlock - 1) / imsim::kBlock))),
+            const uint64_t work = std::max<uint64_t>(seed_pre.back(), (uint64_t)P.n_seeds * W);
+            hipLaunchKernelGGL(imsim::ltg_seed_kernel,
+                               dim3((uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(blocks, (work + imsim::kBlock - 1) / imsim::kBlock))),
                                dim3(imsim::kBlock), 0, s, P, (const uint64_t*)g->d_seed_pre);
             IMS_HIP(hipGetLastError());
         }
@@ -494,7 +543,14 @@ int ims_simulate(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_t
                 if (g->model == IMS_MODEL_IC)
                     hipLaunchKernelGGL(imsim::grid_ic_level_kernel, dim3(blocks), dim3(imsim::kBlock), 0, s, P, st);
                 else
-                    hipLaunchKernelGGL(imsim::grid_lt_sweep_kernel, dim3(blocks), dim3(imsim::kBlock), 0, s, P, st, tau);
+                {
+                    if (lt_mode == 2)
+                        hipLaunchKernelGGL(imsim::ltg_sweep_kernel<2>, dim3(blocks), dim3(imsim::kBlock), 0, s, P, st, tau);
+                    else if (lt_mode == 1)
+                        hipLaunchKernelGGL(imsim::ltg_sweep_kernel<1>, dim3(blocks), dim3(imsim::kBlock), 0, s, P, st, tau);
+                    else
+                        hipLaunchKernelGGL(imsim::ltg_sweep_kernel<0>, dim3(blocks), dim3(imsim::kBlock), 0, s, P, st, tau);
+                }
             }
             IMS_HIP(hipGetLastError());
             // IC: level `end` has no items; LT: sweep end-1 changed nothing
@@ -517,6 +573,11 @@ int ims_simulate(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_t
         }
         IMS_HIP(hipMemcpyAsync(g->d_status, &steps, sizeof steps, hipMemcpyHostToDevice, s));
         IMS_HIP(hipStreamSynchronize(s));
+        if (g->model == IMS_MODEL_LT && cells > 0) {
+            hipLaunchKernelGGL(imsim::ltg_to_word_major, dim3((uint32_t)std::min<uint64_t>((cells + imsim::kBlock - 1) / imsim::kBlock, 65536)),
+                               dim3(imsim::kBlock), 0, s, (const uint64_t*)P.Anm, A, g->n, W);
+            IMS_HIP(hipGetLastError());
+        }
     }
     if (prof) {
         IMS_HIP(hipEventRecord(g->prof_ev[2 * slot + 1], s));

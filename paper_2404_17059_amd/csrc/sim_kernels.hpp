@@ -45,6 +45,8 @@ constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 constexpr uint32_t kChunk = 1024;     // out-arcs per grid-shape IC work item
 constexpr uint32_t kMaxWords = 4096;  // grid-shape queue items carry the word in 12 bits
+constexpr uint32_t kRowWords = 16;   // LT grid shape: words of a source row staged per pass
+constexpr uint32_t kRowPitch = 17;   // LT grid shape: LDS row pitch in uint64 (odd: spreads banks)
 
 struct SimParams {
     int64_t n;
@@ -68,14 +70,26 @@ struct SimParams {
     // LT grid shape: top 16 bits of every threshold hash, [W][n][64] (or null)
     const uint16_t* __restrict__ thp;
     uint32_t thp_shift;  // the table holds hash >> thp_shift (16, or 31 in tests)
+    // LT grid shape: every threshold hash, node-major [n][W][64] (or null)
+    const uint32_t* __restrict__ th32;
+    // LT grid shape, equal in-weights: per (node, trial) the least number of
+    // active in-arc pieces that makes the node join, floor(h / w_v) + 1,
+    // saturated at 255; node-major [n][W][64] (or null)
+    const uint8_t* __restrict__ kmin;
+    // LT grid shape: node batches whose in-arcs fit one 64-arc chunk (or one
+    // node with more); batch b holds nodes bfirst[b] .. bfirst[b+1]-1
+    const uint32_t* __restrict__ bfirst;
+    uint32_t nbatch;
     // state
     uint64_t* A;        // [W][n]
+    uint64_t* Anm;      // LT grid shape: [n][W] (node-major)
     uint64_t* N[3];     // grid IC: next-level masks (rotating); word-local: N[0] only
     uint64_t* Q[3];     // grid IC: queues of (node, word, chunk); word-local: see below
     uint32_t* qcount;   // grid: per-step counters
     uint32_t* aux;      // word-local: per-word scratch (stamps / queue masks)
     const uint32_t* seeds;
     uint32_t n_seeds;
+    uint64_t seed_arcs;  // out-arcs of the seeds (predicts the first sweep's changes)
     uint32_t* task_counter;  // word-local: next word to take
     uint32_t* status;        // [0] max steps over words, [1] guard fired
     uint32_t cap;            // step guard
@@ -187,6 +201,90 @@ __device__ __forceinline__ void lt_count_chunk(const uint64_t (&pend)[8], const 
     }
     if (i < hi) a += __builtin_amdgcn_ubfe(st32[2 * i + half], bitpos, 1);
     cnt[J] = a;
+}
+
+// Sum for node J of a staged LT batch, word slot wl: lane t adds, over the
+// node's in-arcs (positions pre[J] .. pre[J+1]-1 of the staged rows), the
+// weight of each arc whose source is active in trial t.  With equal in-weights
+// it counts the active sources and multiplies once by the node's weight.
+template <int J>
+__device__ __forceinline__ void ltg_sum_staged(const SimParams& P, const uint64_t (&pend)[8], const uint32_t (&pre)[9],
+                                               const uint32_t (&wn)[8], uint64_t (&acc)[8], const uint32_t* R32,
+                                               const uint32_t* WT, uint32_t wl, uint32_t half, uint32_t bitpos)
+{
+    if (pend[J] == 0) return;
+    const uint32_t lo = pre[J], hi = pre[J + 1];
+    const uint32_t* base = R32 + 2 * wl + half;
+    if (P.lt_uniform) {
+        uint32_t c = 0;
+        uint32_t i = lo;
+        for (; i + 1 < hi; i += 2) {
+            const uint32_t b0 = __builtin_amdgcn_ubfe(base[2 * kRowPitch * i], bitpos, 1);
+            const uint32_t b1 = __builtin_amdgcn_ubfe(base[2 * kRowPitch * (i + 1)], bitpos, 1);
+            c = c + b0 + b1;
+        }
+        if (i < hi) c += __builtin_amdgcn_ubfe(base[2 * kRowPitch * i], bitpos, 1);
+        acc[J] = (uint64_t)c * wn[J];
+    } else {
+        uint64_t a = 0;
+        for (uint32_t i = lo; i < hi; ++i)
+            a += (uint32_t)__builtin_amdgcn_sbfe((int)base[2 * kRowPitch * i], bitpos, 1) & WT[i];
+        acc[J] = a;
+    }
+}
+
+// Decide "in-weight > threshold hash" for the pending trials (pend[j], one
+// bit per lane/trial) of up to 8 nodes vsu[j] of word w, given the exact
+// sums acc[j] (this lane's trial).  With the prefix table (hpre[j] = this
+// lane's threshold >> thp_shift) the prefixes settle every trial except a
+// tie; ties, and every trial without a table, compare with the full hash:
+// lane 8j+g draws the Philox block of node vsu[j] for trials 64w+8g .. +7 when
+// that group holds an undecided trial.  Returns the join mask per node.
+__device__ __forceinline__ void lt_decide(const SimParams& P, uint32_t w, uint32_t lane, const uint64_t (&vsu)[8],
+                                          const uint64_t (&pend)[8], const uint64_t (&acc)[8], const uint32_t (&hpre)[8],
+                                          uint64_t (&dec)[8])
+{
+    uint64_t need[8];
+    uint64_t any_need = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        need[j] = 0;
+        dec[j] = 0;
+        if (pend[j] == 0) continue;
+        if (P.thp) {
+            const uint64_t hi = acc[j] >> P.thp_shift;
+            const bool pb = (pend[j] >> lane) & 1ull;
+            dec[j] = __ballot(pb && hi > hpre[j]);
+            need[j] = __ballot(pb && hi == hpre[j]);
+        } else {
+            need[j] = pend[j];
+        }
+        any_need |= need[j];
+    }
+    if (any_need == 0) return;
+    const uint32_t jj = lane >> 3, gg = lane & 7;
+    uint64_t my_need = need[0], my_node = vsu[0];
+#pragma unroll
+    for (int j = 1; j < 8; ++j) {
+        my_need = (jj == (uint32_t)j) ? need[j] : my_need;
+        my_node = (jj == (uint32_t)j) ? vsu[j] : my_node;
+    }
+    Block4 blk{0, 0, 0, 0};
+    if ((my_need >> (8 * gg)) & 0xFFull) blk = philox_block(my_node, (uint64_t)w * 8 + gg, P.seed, kDomainLtNode);
+    const uint32_t src_off = lane >> 3;
+    const uint32_t sel = (lane & 7) >> 1;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        if (need[j] == 0) continue;
+        const int src = 8 * j + (int)src_off;
+        const uint64_t x0 = __shfl(blk.w0, src);
+        const uint64_t x1 = __shfl(blk.w1, src);
+        const uint64_t x2 = __shfl(blk.w2, src);
+        const uint64_t x3 = __shfl(blk.w3, src);
+        const uint64_t word = sel == 0 ? x0 : sel == 1 ? x1 : sel == 2 ? x2 : x3;
+        const uint32_t h = (lane & 1) ? (uint32_t)(word >> 32) : (uint32_t)word;
+        dec[j] |= __ballot(((need[j] >> lane) & 1ull) && acc[j] > (uint64_t)h);
+    }
 }
 
 // LT: evaluate up to 8 nodes of word w with one wavefront, lane = trial;
@@ -323,52 +421,8 @@ __device__ __forceinline__ void lt_eval8_core(const SimParams& P, uint32_t w, ui
         }
     }
 
-    // Decide "in-weight > threshold hash" per pending trial.  With the prefix
-    // table the top 16 bits settle every trial except a tie of the prefixes;
-    // ties (and every trial without a table) compare with the full hash.
-    uint64_t need[8], dec[8];
-    uint64_t any_need = 0;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        need[j] = 0;
-        dec[j] = 0;
-        if (pend[j] == 0) continue;
-        if (P.thp) {
-            const uint32_t hp = hpre[j];
-            const uint64_t hi = acc[j] >> P.thp_shift;
-            const bool pb = (pend[j] >> lane) & 1ull;
-            dec[j] = __ballot(pb && hi > hp);
-            need[j] = __ballot(pb && hi == hp);
-        } else {
-            need[j] = pend[j];
-        }
-        any_need |= need[j];
-    }
-    if (any_need) {
-        // lane 8j+g draws the block of node vs[j] for trials 64w+8g .. +7 when
-        // that group holds an undecided trial
-        const uint32_t jj = lane >> 3, gg = lane & 7;
-        uint64_t my_need = need[0];
-#pragma unroll
-        for (int j = 1; j < 8; ++j) my_need = (jj == (uint32_t)j) ? need[j] : my_need;
-        const uint64_t my_node = __shfl(myv, (int)jj);
-        Block4 blk{0, 0, 0, 0};
-        if ((my_need >> (8 * gg)) & 0xFFull) blk = philox_block(my_node, (uint64_t)w * 8 + gg, P.seed, kDomainLtNode);
-        const uint32_t src_off = lane >> 3;
-        const uint32_t sel = (lane & 7) >> 1;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            if (need[j] == 0) continue;
-            const int src = 8 * j + (int)src_off;
-            const uint64_t x0 = __shfl(blk.w0, src);
-            const uint64_t x1 = __shfl(blk.w1, src);
-            const uint64_t x2 = __shfl(blk.w2, src);
-            const uint64_t x3 = __shfl(blk.w3, src);
-            const uint64_t word = sel == 0 ? x0 : sel == 1 ? x1 : sel == 2 ? x2 : x3;
-            const uint32_t h = (lane & 1) ? (uint32_t)(word >> 32) : (uint32_t)word;
-            dec[j] |= __ballot(((need[j] >> lane) & 1ull) && acc[j] > (uint64_t)h);
-        }
-    }
+    uint64_t dec[8];
+    lt_decide(P, w, lane, vsu, pend, acc, hpre, dec);
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         if (dec[j] == 0) continue;
@@ -391,34 +445,6 @@ __device__ __forceinline__ void lt_eval8(const SimParams& P, uint32_t w, const u
     const int64_t kb = pl ? P.in_off[myv] : 0;
     const uint32_t dg = pl ? (uint32_t)(P.in_off[myv + 1] - kb) : 0u;
     lt_eval8_core(P, w, lane, myv, pl, kb, dg, joined, stage);
-}
-
-// Threshold prefix table for the LT grid shape: thp[(w*n + v)*64 + b] =
-// H(seed, LT, 64w + b, v) >> thp_shift (the top 16 bits for shift 16).  Lane 8j+g of a wavefront draws the block of
-// node 8*item + j for trials 64w+8g .. 64w+8g+7 and stores its eight prefixes.
-__global__ __launch_bounds__(kBlock) void lt_threshold_table_kernel(SimParams P, uint16_t* __restrict__ thp)
-{
-    const uint64_t n = (uint64_t)P.n;
-    const uint64_t nb = (n + 7) / 8;
-    const uint64_t items = nb * P.W;
-    const uint32_t lane = threadIdx.x & 63u;
-    for (uint64_t it = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) >> 6; it < items; it += ((uint64_t)gridDim.x * kBlock) >> 6) {
-        const uint32_t w = (uint32_t)(it / nb);
-        const uint64_t v = (it % nb) * 8 + (lane >> 3);
-        const uint32_t g = lane & 7;
-        if (v >= n) continue;
-        const Block4 b = philox_block(v, (uint64_t)w * 8 + g, P.seed, kDomainLtNode);
-        const uint32_t sh = P.thp_shift;
-        auto pair = [sh](uint64_t x) -> uint32_t {
-            return (((uint32_t)x) >> sh) | ((((uint32_t)(x >> 32)) >> sh) << 16);
-        };
-        uint4 out;
-        out.x = pair(b.w0);
-        out.y = pair(b.w1);
-        out.z = pair(b.w2);
-        out.w = pair(b.w3);
-        *reinterpret_cast<uint4*>(thp + ((uint64_t)w * n + v) * 64 + 8 * g) = out;
-    }
 }
 
 // =========================================================== grid shape
@@ -450,25 +476,6 @@ __global__ __launch_bounds__(kBlock) void grid_seed_kernel(SimParams P, int mode
             P.N[0][(uint64_t)w * n + s] = vm;
             grid_ic_enqueue(P, P.Q[0], &P.qcount[0], s, w);
         }
-    }
-}
-
-// LT: mark the out-neighbours of the seeds for sweep 0 (mark value 1) in every
-// word.  Threads run over the concatenated out-arcs of the seeds;
-// seed_arc_pre[i] is the number of seed out-arcs before seed i.
-__global__ __launch_bounds__(kBlock) void grid_lt_seed_mark_kernel(SimParams P, const uint64_t* __restrict__ seed_arc_pre)
-{
-    const uint64_t n = (uint64_t)P.n;
-    const uint64_t total = seed_arc_pre[P.n_seeds];
-    for (uint64_t q = (uint64_t)blockIdx.x * kBlock + threadIdx.x; q < total; q += (uint64_t)gridDim.x * kBlock) {
-        uint32_t lo = 0, hi = P.n_seeds;  // last seed with seed_arc_pre[i] <= q
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (seed_arc_pre[mid] <= q) lo = mid; else hi = mid;
-        }
-        const uint32_t s = P.seeds[lo];
-        const uint32_t v = P.idx[P.off[s] + (int64_t)(q - seed_arc_pre[lo])];
-        for (uint32_t w = 0; w < P.W; ++w) P.aux[(uint64_t)w * n + v] = 1u;
     }
 }
 
@@ -526,73 +533,370 @@ __global__ __launch_bounds__(kBlock) void grid_ic_level_kernel(SimParams P, uint
     }
 }
 
-// LT sweep `sw`, in place over all words.  Direction switch: a sweep "marks"
-// when the previous sweep changed fewer than `tau` (node, word) pairs: every
-// node that joins then stamps its out-neighbours with sw + 2 in aux.  A sweep
-// that follows a marking sweep evaluates only nodes stamped >= sw + 1 (sweep 0
-// follows the seed marks); any other sweep evaluates every node with an
-// inactive trial.  Nodes whose in-neighbours did not change since their last
-// evaluation cannot change, so both forms reach the same fixpoint.  A sweep
-// that follows one without change returns at once.  qcount[sw] counts the
-// (node, word) pairs that changed.
-__global__ __launch_bounds__(kBlock) void grid_lt_sweep_kernel(SimParams P, uint32_t sw, uint32_t tau)
+// Bits lo .. hi-1 of a 64-bit word (0 when empty).
+__device__ __forceinline__ uint64_t range_of(uint32_t lo, uint32_t hi)
 {
-    __shared__ ArcStage stage[kWaves][64];
+    return hi <= lo ? 0ull : (hi >= 64 ? ~0ull : ((1ull << hi) - 1ull)) & ~((1ull << lo) - 1ull);
+}
+
+// 64x64 bit transpose across a wavefront: on entry lane i holds row i, on exit
+// lane t holds column t (bit i of the result = bit t of lane i's input).  Six
+// rounds swap the off-diagonal blocks of side s = 32, 16, ..., 1 between lanes
+// L and L ^ s.
+__device__ __forceinline__ uint64_t wave_transpose64(uint64_t x, uint32_t lane)
+{
+    constexpr uint64_t kHi[6] = {0xFFFFFFFF00000000ull, 0xFFFF0000FFFF0000ull, 0xFF00FF00FF00FF00ull,
+                                 0xF0F0F0F0F0F0F0F0ull, 0xCCCCCCCCCCCCCCCCull, 0xAAAAAAAAAAAAAAAAull};
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+        const uint32_t sft = 32u >> r;
+        const uint64_t m = kHi[r];  // bit positions k with (k & sft) != 0
+        const uint64_t y = __shfl_xor(x, (int)sft);
+        // branch-free: upper lanes keep their m-bits and take the partner's
+        // other bits shifted down; lower lanes the mirror image
+        const uint64_t upper = 0ull - (uint64_t)((lane & sft) != 0);
+        const uint64_t keep = (m & upper) | (~m & ~upper);
+        const uint64_t moved = ((y >> sft) & upper) | ((y << sft) & ~upper);
+        x = (x & keep) | (moved & ~keep);
+    }
+    return x;
+}
+
+// ============================================== LT grid shape, node-major
+//
+// For the grid shape the LT state is kept node-major, Anm[v*W + w], so the
+// masks of one source for all words share cache lines.  A wavefront takes a
+// batch of up to 8 consecutive nodes whose in-arcs fit one 64-arc chunk,
+// loads the mask row of every in-arc source once (16 words at a time) into
+// LDS, and then evaluates the batch word by word from LDS.  Batches of one
+// node with more than 64 in-arcs gather one word at a time instead.
+
+// Seeds are active in every trial; their out-neighbours are marked (value 1)
+// for sweep 0.  seed_arc_pre[i] = number of seed out-arcs before seed i.
+__global__ __launch_bounds__(kBlock) void ltg_seed_kernel(SimParams P, const uint64_t* __restrict__ seed_arc_pre)
+{
+    const uint64_t W = P.W;
+    const uint64_t gt = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    const uint64_t nt = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t i = gt; i < (uint64_t)P.n_seeds * W; i += nt) {
+        const uint32_t s = P.seeds[i / W];
+        const uint32_t w = (uint32_t)(i % W);
+        P.Anm[(uint64_t)s * W + w] = valid_mask(w, P.W, P.T);
+    }
+    const uint64_t total = seed_arc_pre[P.n_seeds];
+    for (uint64_t q = gt; q < total; q += nt) {
+        uint32_t lo = 0, hi = P.n_seeds;  // last seed with seed_arc_pre[i] <= q
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (seed_arc_pre[mid] <= q) lo = mid; else hi = mid;
+        }
+        const uint32_t s = P.seeds[lo];
+        const uint64_t v = P.idx[P.off[s] + (int64_t)(q - seed_arc_pre[lo])];
+        for (uint64_t w = 0; w < W; ++w) P.aux[v * W + w] = 1u;
+    }
+}
+
+// Threshold table, node-major: th32[(v*W + w)*64 + b] = H(seed, LT, 64w + b, v).
+// Lane 8j+g of a wavefront draws the block of node 8*item + j for trials
+// 64w+8g .. 64w+8g+7 and stores its eight hashes (32 bytes).
+__global__ __launch_bounds__(kBlock) void ltg_table_kernel(SimParams P, uint32_t* __restrict__ th32)
+{
+    const uint64_t n = (uint64_t)P.n;
+    const uint64_t W = P.W;
+    const uint64_t items = ((n + 7) / 8) * W;
+    const uint32_t lane = threadIdx.x & 63u;
+    for (uint64_t it = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) >> 6; it < items; it += ((uint64_t)gridDim.x * kBlock) >> 6) {
+        const uint32_t w = (uint32_t)(it % W);
+        const uint64_t v = (it / W) * 8 + (lane >> 3);
+        const uint32_t g = lane & 7;
+        if (v >= n) continue;
+        const Block4 b = philox_block(v, (uint64_t)w * 8 + g, P.seed, kDomainLtNode);
+        uint4* dst = reinterpret_cast<uint4*>(th32 + (v * W + w) * 64 + 8 * g);
+        dst[0] = make_uint4((uint32_t)b.w0, (uint32_t)(b.w0 >> 32), (uint32_t)b.w1, (uint32_t)(b.w1 >> 32));
+        dst[1] = make_uint4((uint32_t)b.w2, (uint32_t)(b.w2 >> 32), (uint32_t)b.w3, (uint32_t)(b.w3 >> 32));
+    }
+}
+
+// Count-threshold table (equal in-weights): kmin[(v*W + w)*64 + b] =
+// min(255, floor(H(seed, LT, 64w + b, v) / w_v) + 1): with c active in-arc
+// pieces of weight w_v, c * w_v > h exactly when c >= floor(h / w_v) + 1.
+__global__ __launch_bounds__(kBlock) void ltg_kmin_kernel(SimParams P, uint8_t* __restrict__ kmin)
+{
+    const uint64_t n = (uint64_t)P.n;
+    const uint64_t W = P.W;
+    const uint64_t items = ((n + 7) / 8) * W;
+    const uint32_t lane = threadIdx.x & 63u;
+    for (uint64_t it = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) >> 6; it < items; it += ((uint64_t)gridDim.x * kBlock) >> 6) {
+        const uint32_t w = (uint32_t)(it % W);
+        const uint64_t v = (it / W) * 8 + (lane >> 3);
+        const uint32_t g = lane & 7;
+        if (v >= n) continue;
+        const uint32_t wv = P.node_w[v];
+        const Block4 b = philox_block(v, (uint64_t)w * 8 + g, P.seed, kDomainLtNode);
+        uint32_t packed[2] = {0, 0};
+#pragma unroll
+        for (uint32_t i = 0; i < 8; ++i) {
+            const uint32_t h = block_lane(b, i);
+            const uint32_t k = wv == 0 ? 255u : (h / wv >= 254u ? 255u : h / wv + 1u);
+            packed[i >> 2] |= k << (8 * (i & 3));
+        }
+        *reinterpret_cast<uint2*>(kmin + (v * W + w) * 64 + 8 * g) = make_uint2(packed[0], packed[1]);
+    }
+}
+
+// LT sweep `sw` over all words, in place.  Direction switch: a sweep "marks"
+// when the previous sweep changed fewer than `tau` (node, word) pairs: every
+// node that joins then stamps its out-neighbours with sw + 2 in aux (node-
+// major).  A sweep that follows a marking sweep evaluates only nodes stamped
+// >= sw + 1 (sweep 0 follows the seed marks); any other sweep evaluates every
+// node with an inactive trial.  A node none of whose in-neighbours changed
+// since its last evaluation cannot change, so both forms reach the same
+// fixpoint.  A sweep that follows one without change returns at once.
+// qcount[sw] counts the (node, word) pairs that changed.
+// kMode: 0 = threshold hashes drawn in the kernel, 1 = threshold table,
+// 2 = count-threshold table (equal in-weights; long rows draw hashes).
+template <int kMode>
+__global__ __launch_bounds__(kBlock) void ltg_sweep_kernel(SimParams P, uint32_t sw, uint32_t tau)
+{
+    __shared__ uint64_t rows[kWaves][64 * kRowPitch];
+    __shared__ uint32_t wts[kWaves][64];
     if (sw >= 1 && load_relaxed32(&P.qcount[sw - 1]) == 0) return;
     if (sw >= P.cap) {
         if (blockIdx.x == 0 && threadIdx.x == 0) P.status[1] = 1;
         return;
     }
-    // changes of sweep x (x = -1: seed pairs)
-    auto changes = [&](int64_t x) -> uint32_t {
-        return x < 0 ? P.n_seeds * P.W : load_relaxed32(&P.qcount[x]);
+    // changes of sweep x; before sweep 0, the seeds' out-arcs times the words
+    // stand for the pairs sweep 0 may change
+    auto changes = [&](int64_t x) -> uint64_t {
+        return x < 0 ? P.seed_arcs * P.W : (uint64_t)load_relaxed32(&P.qcount[x]);
     };
     const bool marks_now = changes((int64_t)sw - 1) < tau;
     const bool marked_only = sw == 0 ? true : changes((int64_t)sw - 2) < tau;
+    const uint32_t min_mark = sw + 1;
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = threadIdx.x >> 6;
-    const uint64_t n = (uint64_t)P.n;
-    // wavefronts take blocks of 64 nodes of one word, find the 8-node batches
-    // with a node to evaluate, and evaluate those
-    const uint64_t nb = (n + 63) / 64;
-    const uint64_t items = nb * P.W;
+    const uint64_t W = P.W;
+    uint64_t* R = rows[wave];
+    const uint32_t* R32 = reinterpret_cast<const uint32_t*>(rows[wave]);
+    uint32_t* WT = wts[wave];
+    const uint32_t half = lane >> 5, bitpos = lane & 31u;
     const uint64_t gwave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
     const uint64_t nwaves = ((uint64_t)gridDim.x * kBlock) >> 6;
     uint32_t changed = 0;
-    for (uint64_t it = gwave; it < items; it += nwaves) {
-        const uint32_t w = (uint32_t)(it / nb);
-        const uint64_t vbase = (it % nb) * 64;
-        const uint64_t vm = valid_mask(w, P.W, P.T);
-        const uint64_t v = vbase + lane;
-        const bool inr = v < n;
-        uint64_t p = inr ? (vm & ~load_relaxed(&P.A[(uint64_t)w * n + v])) : 0ull;
-        const int64_t kb = inr ? P.in_off[v] : 0;
-        const int64_t ke = inr ? P.in_off[v + 1] : 0;
-        if (p && marked_only && P.aux[(uint64_t)w * n + v] < sw + 1) p = 0;
-        const uint64_t bm = __ballot(p != 0);
-        if (bm == 0) continue;
-        for (uint32_t b8 = 0; b8 < 8; ++b8) {
-            if (((bm >> (8 * b8)) & 0xFFull) == 0) continue;
-            const int src = (int)(8 * b8 + (lane & 7));
-            const uint64_t myv = __shfl(v, src);
-            const uint64_t pl = __shfl(p, src);
-            const int64_t kbj = __shfl(kb, src);
-            const uint32_t dg = (uint32_t)(__shfl(ke, src) - kbj);
-            uint64_t joined[8];
-            lt_eval8_core(P, w, lane, myv, pl, kbj, dg, joined, stage[wave]);
+
+    for (uint64_t bi = gwave; bi < P.nbatch; bi += nwaves) {
+        const uint32_t vf = uniform32(P.bfirst[bi]);
+        const uint32_t nn = uniform32(P.bfirst[bi + 1]) - vf;
+        const bool own = lane < nn;
+        const uint64_t myv = own ? (uint64_t)vf + lane : 0ull;
+        const int64_t kb = own ? P.in_off[myv] : 0;
+        const uint32_t dg = own ? (uint32_t)(P.in_off[myv + 1] - kb) : 0u;
+        uint32_t incl = dg;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                if (joined[j] == 0) continue;
-                ++changed;
-                if (marks_now) {
-                    const uint64_t vj = vbase + 8 * b8 + j;
-                    uint32_t* mk = P.aux + (uint64_t)w * n;
-                    for (int64_t e = P.off[vj] + lane; e < P.off[vj + 1]; e += 64) mk[P.idx[e]] = sw + 2;
+        for (int o = 1; o < 8; o <<= 1) {
+            const uint32_t y = __shfl_up(incl, o);
+            incl += lane >= (uint32_t)o ? y : 0u;
+        }
+        const uint32_t pre_lane = incl - dg;
+        const uint32_t total = uniform32(__shfl(incl, 7));
+        if (total == 0) continue;  // no in-weight: these nodes never join
+        const bool big = total > 64;  // a single node with a long in-arc row
+        uint32_t wn_lane = 0;
+        if (own && P.lt_uniform) wn_lane = P.node_w[myv];
+        // this lane's in-arc (for the staged form): node, then row position
+        uint32_t j_of = 0;
+#pragma unroll
+        for (int jj = 1; jj < 8; ++jj) j_of += (lane >= (uint32_t)__builtin_amdgcn_readlane((int)pre_lane, jj)) ? 1u : 0u;
+        const uint32_t pj = __shfl(pre_lane, (int)j_of);
+        const int64_t kbj = __shfl(kb, (int)j_of);
+        const uint64_t my_arc = (uint64_t)kbj + (lane - pj);
+
+        for (uint32_t wg = 0; wg < P.W; wg += kRowWords) {
+            const uint32_t gw = P.W - wg < kRowWords ? P.W - wg : kRowWords;
+            // words of this group with a node to evaluate: lane 8j+x holds the
+            // decidable trials of node j, word wg+x (pn0) and wg+x+8 (pn1)
+            uint64_t pn0 = 0, pn1 = 0;
+            uint32_t wmask = 0;
+#pragma unroll
+            for (uint32_t pass = 0; pass < 2; ++pass) {
+                const uint32_t j = lane >> 3, wl = (lane & 7) + 8 * pass;
+                uint64_t pn = 0;
+                if (j < nn && wl < gw) {
+                    const uint64_t v = (uint64_t)vf + j;
+                    const uint32_t w = wg + wl;
+                    pn = valid_mask(w, P.W, P.T) & ~load_relaxed(&P.Anm[v * W + w]);
+                    if (pn && marked_only && P.aux[v * W + w] < min_mark) pn = 0;
+                }
+                if (pass) pn1 = pn; else pn0 = pn;
+                uint64_t b = __ballot(pn != 0);
+                b |= b >> 32;
+                b |= b >> 16;
+                b |= b >> 8;
+                wmask |= (uint32_t)(b & 0xFFull) << (8 * pass);
+            }
+            wmask = uniform32(wmask);
+            if (wmask == 0) continue;
+            // pending trials of node j at word slot wl (uniform)
+            auto pend_of = [&](uint32_t j, uint32_t wl) -> uint64_t {
+                const uint64_t x = wl >= 8 ? pn1 : pn0;
+                const int src = (int)(8 * j + (wl & 7));
+                return (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, src) |
+                       ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), src) << 32);
+            };
+            if (!big) {
+                // stage the mask rows (this word group) of all in-arc sources
+                uint32_t src = 0, wt = 0;
+                if (lane < total) {
+                    if (P.lt_uniform) {
+                        src = P.in_src32[my_arc];
+                    } else {
+                        const uint64_t arc = P.in_arc[my_arc];
+                        src = (uint32_t)arc;
+                        wt = (uint32_t)(arc >> 32);
+                    }
+                }
+                // plain loads: a mask read stale within a sweep only delays a
+                // join to the next sweep, and a sweep without joins saw the
+                // state its launch started from
+                uint64_t row[kRowWords];
+                const uint64_t* rp = P.Anm + (uint64_t)src * W + wg;
+                if ((W & 1) == 0 && gw == kRowWords) {
+                    const uint4* rp4 = reinterpret_cast<const uint4*>(rp);
+#pragma unroll
+                    for (uint32_t x = 0; x < kRowWords / 2; ++x) {
+                        const uint4 q = lane < total ? rp4[x] : make_uint4(0, 0, 0, 0);
+                        row[2 * x] = (uint64_t)q.x | ((uint64_t)q.y << 32);
+                        row[2 * x + 1] = (uint64_t)q.z | ((uint64_t)q.w << 32);
+                    }
+                } else {
+#pragma unroll
+                    for (uint32_t x = 0; x < kRowWords; ++x) row[x] = (lane < total && x < gw) ? rp[x] : 0ull;
+                }
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                for (uint32_t x = 0; x < kRowWords; ++x) R[lane * kRowPitch + x] = row[x];
+                WT[lane] = wt;
+                __builtin_amdgcn_wave_barrier();
+            }
+            uint32_t wm = wmask;
+            uint32_t kpn0 = 0, kpn1 = 0;
+            if (kMode == 2) {
+                const uint32_t w0 = wg + (uint32_t)__builtin_ctz(wm);
+                for (uint32_t j = 0; j < nn; ++j) {
+                    const uint32_t kv = P.kmin[((uint64_t)(vf + j) * W + w0) * 64 + lane];
+                    if (j < 4) kpn0 |= kv << (8 * j); else kpn1 |= kv << (8 * (j - 4));
                 }
             }
+            while (wm) {
+                const uint32_t wl = (uint32_t)__builtin_ctz(wm);
+                wm &= wm - 1;
+                const uint32_t w = wg + wl;
+                // equal in-weights: transpose the staged masks of this word so
+                // that lane t holds "arc i active in trial t" as bit i; a node's
+                // count is then the popcount of its arc range
+                uint64_t colbits = 0;
+                if (P.lt_uniform && !big)
+                    colbits = wave_transpose64(lane < total ? R[lane * kRowPitch + wl] : 0ull, lane);
+                constexpr bool kTable = kMode == 1;
+                // count thresholds of the next word's nodes (two packed
+                // registers) are fetched while this word is evaluated
+                uint32_t kpack0 = kpn0, kpack1 = kpn1;
+                if (kMode == 2 && wm) {
+                    const uint32_t wn2 = wg + (uint32_t)__builtin_ctz(wm);
+                    kpn0 = 0;
+                    kpn1 = 0;
+                    for (uint32_t j = 0; j < nn; ++j) {
+                        const uint32_t kv = P.kmin[((uint64_t)(vf + j) * W + wn2) * 64 + lane];
+                        if (j < 4) kpn0 |= kv << (8 * j); else kpn1 |= kv << (8 * (j - 4));
+                    }
+                }
+                // nodes one at a time; with the threshold table the next node's
+                // threshold is fetched while the current one is summed
+                auto th_of = [&](uint32_t j) -> uint32_t {
+                    return (kTable && j < nn && pend_of(j, wl)) ? P.th32[((uint64_t)(vf + j) * W + w) * 64 + lane] : 0u;
+                };
+                uint32_t h_next = th_of(0);
+                for (uint32_t j = 0; j < nn; ++j) {
+                    const uint32_t h_tab = h_next;
+                    h_next = th_of(j + 1);
+                    const uint64_t pend = pend_of(j, wl);
+                    if (pend == 0) continue;
+                    const uint64_t v = (uint64_t)vf + j;
+                    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)pre_lane, (int)j);
+                    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)incl, (int)j);
+                    uint64_t acc = 0;
+                    if (!big) {
+                        const uint32_t* base = R32 + 2 * wl + half;
+                        if (P.lt_uniform) {
+                            if (kMode != 2) {
+                                const uint32_t c = (uint32_t)__popcll(colbits & range_of(lo, hi));
+                                acc = (uint64_t)c * (uint32_t)__builtin_amdgcn_readlane((int)wn_lane, (int)j);
+                            }
+                        } else {
+                            for (uint32_t i = lo; i < hi; ++i)
+                                acc += (uint32_t)__builtin_amdgcn_sbfe((int)base[2 * kRowPitch * i], bitpos, 1) & WT[i];
+                        }
+                    } else {
+                        // one node: gather this word's source masks 64 arcs at a time
+                        const int64_t kb0 = uniform64((uint64_t)__shfl(kb, 0));
+                        for (uint32_t c = 0; c < total; c += 64) {
+                            const uint32_t q = c + lane;
+                            uint32_t src = 0, wt = 0;
+                            if (q < total) {
+                                const uint64_t arc = P.in_arc[(uint64_t)kb0 + q];
+                                src = (uint32_t)arc;
+                                wt = (uint32_t)(arc >> 32);
+                            }
+                            const uint64_t a = q < total ? load_relaxed(&P.Anm[(uint64_t)src * W + w]) : 0ull;
+                            __builtin_amdgcn_wave_barrier();
+                            R[lane * kRowPitch] = a;
+                            WT[lane] = wt;
+                            __builtin_amdgcn_wave_barrier();
+                            const uint32_t cnt = total - c < 64 ? total - c : 64;
+                            for (uint32_t i = 0; i < cnt; ++i) {
+                                const uint32_t h32 = R32[2 * (i * kRowPitch) + half];
+                                acc += (uint32_t)__builtin_amdgcn_sbfe((int)h32, bitpos, 1) & WT[i];
+                            }
+                            __builtin_amdgcn_wave_barrier();
+                        }
+                    }
+                    // this lane's trial: join when the in-weight exceeds its hash
+                    bool join;
+                    if (kMode == 2 && !big) {
+                        const uint32_t kj = ((j < 4 ? kpack0 : kpack1) >> (8 * (j & 3))) & 0xFFu;
+                        const uint32_t c = (uint32_t)__popcll(colbits & range_of(lo, hi));
+                        join = c >= kj;
+                    } else {
+                        uint32_t h = h_tab;
+                        if (kMode != 1) {
+                            const Block4 blk = philox_block(v, (uint64_t)w * 8 + (lane >> 3), P.seed, kDomainLtNode);
+                            h = block_lane(blk, lane & 7);
+                        }
+                        join = acc > (uint64_t)h;
+                    }
+                    const uint64_t dec = __ballot(((pend >> lane) & 1ull) && join);
+                    if (dec == 0) continue;
+                    if (lane == 0) atomic_or64(&P.Anm[v * W + w], dec);
+                    ++changed;
+                    if (marks_now)
+                        for (int64_t e = P.off[v] + lane; e < P.off[v + 1]; e += 64) P.aux[(uint64_t)P.idx[e] * W + w] = sw + 2;
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
         }
     }
     if (changed && lane == 0) atomicAdd(&P.qcount[sw], changed);
+}
+
+// Word-major copy of the node-major state: A[w*n + v] = Anm[v*W + w].
+__global__ __launch_bounds__(kBlock) void ltg_to_word_major(const uint64_t* __restrict__ Anm, uint64_t* __restrict__ A, int64_t n,
+                                                          uint32_t W)
+{
+    const uint64_t total = (uint64_t)n * W;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += (uint64_t)gridDim.x * kBlock) {
+        const uint64_t w = i / (uint64_t)n, v = i % (uint64_t)n;
+        A[i] = Anm[v * W + w];
+    }
 }
 
 // ====================================================== word-local shape

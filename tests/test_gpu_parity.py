@@ -173,12 +173,12 @@ def test_both_shapes_on_random_graphs(ims, model, shape):
     run_both(ims, model, n, off, idx, param, np.array([3, 9, 27], np.uint32), 333, 17, opts=opts)
 
 
-@pytest.mark.parametrize("flags,alpha", [(0, 0.0), (1, 0.0), (2, 0.0), (2, 1.0), (0, 1e-9), (4, 0.0), (6, 0.0), (5, 1.0)])
+@pytest.mark.parametrize("flags,alpha", [(0, 0.0), (1, 0.0), (8, 0.0), (8, 1.0), (0, 1.0), (0, 1e-9), (4, 0.0), (5, 1.0)])
 def test_lt_grid_threshold_paths_and_direction_switch(ims, flags, alpha):
-    """LT grid shape with the threshold prefix table, without it, with 1-bit
-    prefixes (exact tie path on about half the trials), with and without the
-    equal-in-weights counting form, and with the marking direction always on
-    (alpha=1) or always off (alpha tiny): identical bits."""
+    """LT grid shape with count thresholds, full threshold hashes, hashes drawn
+    in the kernel, with and without the equal-in-weights counting form, and
+    with the marking direction always on (alpha=1) or always off (alpha
+    tiny): identical bits."""
     g = synth.chung_lu_directed(20000, 2.1, 8.0, seed=31)
     param = synth.weighted_cascade(g)
     seeds = synth.top_outdeg_seeds(g, 20)
