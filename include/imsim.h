@@ -120,6 +120,24 @@ int ims_simulate(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_t
                  uint64_t rng_seed, const ims_opts* opts, uint32_t* trial_counts,
                  uint32_t* node_counts, uint64_t* total, uint64_t* active_bits, void* stream);
 
+/* Many seed sets on one graph with common random numbers (every set sees the
+ * same coins / thresholds: same rng_seed and trials 0 .. n_trials-1), as the
+ * greedy and CELF influence maximisation of Section 2 evaluate sigma(S + v)
+ * for many v.
+ *   set_offsets  host uint32[n_sets+1]: set i is set_nodes[set_offsets[i] ..
+ *                set_offsets[i+1]); set_offsets[0] == 0, non-decreasing.
+ *   set_nodes    host uint32[set_offsets[n_sets]]; duplicates within a set are
+ *                ignored; ids must be < n.  Empty sets are allowed.
+ *   totals       device uint64[n_sets]: sum over trials of |A_t(set)|;
+ *                sigma(set) = totals[i] / n_trials.              required
+ *   node_counts  device uint32[n_sets * n]: per set, trials in which each
+ *                node ended active.                               optional (NULL)
+ * Every set's results equal those of ims_simulate on that set.  Asynchronous
+ * on `stream`. */
+int ims_simulate_sets(ims_graph* g, const uint32_t* set_offsets, const uint32_t* set_nodes, uint32_t n_sets,
+                      uint32_t n_trials, uint64_t rng_seed, const ims_opts* opts, uint64_t* totals,
+                      uint32_t* node_counts, void* stream);
+
 /* Status of the last run on this handle: out[0] = steps (IC frontier levels
  * or LT sweeps) taken, out[1] = nonzero if the step guard fired.  Waits for
  * `stream`. */

@@ -55,6 +55,7 @@ _sig("ims_graph_destroy", _int, _P)
 _sig("ims_graph_info", _int, _P, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_int))
 _sig("ims_simulate", _int, _P, _P, _u32, _u32, _u64, ctypes.POINTER(Opts), _P, _P, _P, _P, _P)
 _sig("ims_graph_last_status", _int, _P, _P, _P)
+_sig("ims_simulate_sets", _int, _P, _P, _P, _u32, _u32, _u64, ctypes.POINTER(Opts), _P, _P, _P)
 _sig("ims_graph_profile", _int, _P, _int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_u32))
 _sig("ims_debug_hash", _int, _u64, _u64, _P, _P, _P, _i64, _P)
 
@@ -196,6 +197,47 @@ def simulate(graph: Graph, seeds, n_trials: int, rng_seed: int, want_bits: bool 
     total = int(tot.item())
     return {"trial_counts": tc, "total": total, "mean": total / T, "node_counts": nc,
             "active_bits": bits, "steps": steps}
+
+
+def pack_sets(sets) -> tuple[np.ndarray, np.ndarray]:
+    """Concatenate seed sets into (offsets uint32[k+1], nodes uint32)."""
+    offs = np.zeros(len(sets) + 1, dtype=np.uint32)
+    parts = []
+    for i, st in enumerate(sets):
+        a = np.ascontiguousarray(st, dtype=np.uint32).ravel()
+        parts.append(a)
+        offs[i + 1] = offs[i] + a.shape[0]
+    nodes = np.concatenate(parts) if parts else np.zeros(0, dtype=np.uint32)
+    return offs, np.ascontiguousarray(nodes, dtype=np.uint32)
+
+
+def simulate_sets_into(graph: Graph, offsets: np.ndarray, nodes: np.ndarray, n_trials: int, rng_seed: int,
+                       totals, node_counts=None, stream=None, opts: Opts | None = None) -> None:
+    """Enqueue the simulation of many seed sets (common random numbers)."""
+    n_sets = int(offsets.shape[0]) - 1
+    ptr = lambda t: None if t is None else ctypes.c_void_p(t.data_ptr())
+    _check(_lib.ims_simulate_sets(graph.handle, _np_ptr(offsets), _np_ptr(nodes) if nodes.size else None, n_sets,
+                                  int(n_trials), int(rng_seed) & ((1 << 64) - 1),
+                                  ctypes.byref(opts) if opts is not None else None,
+                                  ptr(totals), ptr(node_counts), _stream_handle(stream)), "ims_simulate_sets")
+
+
+def simulate_sets(graph: Graph, sets, n_trials: int, rng_seed: int, want_node_counts: bool = False,
+                  stream=None, opts: Opts | None = None) -> dict:
+    """sigma of every seed set in `sets` under the same trials (common random
+    numbers); returns host arrays."""
+    torch = _torch()
+    offs, nodes = pack_sets(sets)
+    n_sets = len(sets)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    tot = torch.empty(max(n_sets, 1), dtype=torch.int64, device=dev)
+    nc = torch.empty((max(n_sets, 1), graph.n), dtype=torch.int32, device=dev) if want_node_counts else None
+    simulate_sets_into(graph, offs, nodes, n_trials, rng_seed, tot, nc, stream, opts)
+    totals = tot.cpu().numpy()[:n_sets]
+    out = {"totals": totals, "sigma": totals / float(n_trials)}
+    if want_node_counts:
+        out["node_counts"] = nc.cpu().numpy().view(np.uint32)[:n_sets]
+    return out
 
 
 def debug_hash(rng_seed: int, domain: int, trials, ids) -> np.ndarray:

@@ -98,6 +98,9 @@ struct ims_graph {
         uint64_t bytes = 0;
     };
     Buf A, N[3], Q[3], aux, thp, Anm;
+    // sets mode (ims_simulate_sets): per-slot state
+    Buf sA, sN, sQ[3], sact, sstamp, ssteps, sets_dev;
+    bool sets_zero_dirty = true;  // sN / sstamp / ssteps must start zeroed
     bool zero_dirty = true;  // N / aux must be zero between runs
     uint32_t* d_qcount = nullptr;
     uint32_t cap = 0;
@@ -129,6 +132,7 @@ struct ims_graph {
         release(aux);
         release(thp);
         release(Anm);
+        for (Buf* b : {&sA, &sN, &sQ[0], &sQ[1], &sQ[2], &sact, &sstamp, &ssteps, &sets_dev}) release(*b);
         dev_free(d_off);
         dev_free(d_idx);
         dev_free(d_thr);
@@ -486,6 +490,14 @@ int ims_simulate(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_t
     P.n_seeds = (uint32_t)sv.size();
     P.seed_arcs = seed_pre.back();
     P.task_counter = g->d_status + 2;
+    P.set_off = nullptr;
+    P.set_nodes = nullptr;
+    P.n_sets = 0;
+    P.totals = nullptr;
+    P.set_node_counts = nullptr;
+    P.act = nullptr;
+    P.sstamp = nullptr;
+    P.slot_steps = nullptr;
     P.status = g->d_status;
     P.cap = g->cap;
 
@@ -500,9 +512,9 @@ int ims_simulate(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_t
         const int per_cu = opts && opts->blocks_per_cu > 0 ? opts->blocks_per_cu : 2;
         const uint32_t blocks = std::min<uint32_t>(W, (uint32_t)(g->cus * per_cu));
         if (g->model == IMS_MODEL_IC)
-            hipLaunchKernelGGL(imsim::word_ic_kernel, dim3(blocks), dim3(imsim::kBlock), 0, s, P, n);
+            hipLaunchKernelGGL(imsim::word_ic_kernel<false>, dim3(blocks), dim3(imsim::kBlock), 0, s, P, n);
         else
-            hipLaunchKernelGGL(imsim::word_lt_kernel, dim3(blocks), dim3(imsim::kBlock), 0, s, P, n);
+            hipLaunchKernelGGL(imsim::word_lt_kernel<false>, dim3(blocks), dim3(imsim::kBlock), 0, s, P, n);
         IMS_HIP(hipGetLastError());
     } else {
         const int per_cu = opts && opts->blocks_per_cu > 0 ? opts->blocks_per_cu : 8;
@@ -594,6 +606,110 @@ int ims_simulate(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_t
                            g->n, W, node_counts, (unsigned long long*)total);
         IMS_HIP(hipGetLastError());
     }
+    return IMS_OK;
+}
+
+int ims_simulate_sets(ims_graph* g, const uint32_t* set_offsets, const uint32_t* set_nodes, uint32_t n_sets, uint32_t n_trials,
+                      uint64_t rng_seed, const ims_opts* opts, uint64_t* totals, uint32_t* node_counts, void* stream)
+{
+    if (!g) return fail(IMS_E_INVALID_ARG, "ims_simulate_sets: NULL graph");
+    if (n_trials == 0) return fail(IMS_E_INVALID_ARG, "ims_simulate_sets: n_trials must be >= 1");
+    if (n_trials > imsim::kMaxWords * 64u) return fail(IMS_E_UNSUPPORTED, "ims_simulate_sets: n_trials above %u", imsim::kMaxWords * 64u);
+    if (n_sets > 0 && (!set_offsets || !totals)) return fail(IMS_E_INVALID_ARG, "ims_simulate_sets: set_offsets and totals are required");
+    if (n_sets == 0) return IMS_OK;
+    if (set_offsets[0] != 0) return fail(IMS_E_INVALID_ARG, "ims_simulate_sets: set_offsets[0] must be 0");
+    for (uint32_t i = 0; i < n_sets; ++i)
+        if (set_offsets[i + 1] < set_offsets[i]) return fail(IMS_E_INVALID_ARG, "ims_simulate_sets: set_offsets decrease at %u", i);
+    if (set_offsets[n_sets] > 0 && !set_nodes) return fail(IMS_E_INVALID_ARG, "ims_simulate_sets: set_nodes is NULL");
+    const uint32_t W = (n_trials + 63) / 64;
+    if ((uint64_t)n_sets * W >= 0xFFFFFFFFull) return fail(IMS_E_UNSUPPORTED, "ims_simulate_sets: too many (set, word) tasks");
+    hipStream_t s = (hipStream_t)stream;
+    int rc = device_cus(g);
+    if (rc) return rc;
+    // set semantics per set: sort, drop duplicates, check the range
+    std::vector<uint32_t> off(1, 0), nodes;
+    nodes.reserve(set_offsets[n_sets]);
+    for (uint32_t i = 0; i < n_sets; ++i) {
+        const size_t b = nodes.size();
+        for (uint32_t k = set_offsets[i]; k < set_offsets[i + 1]; ++k) {
+            if ((int64_t)set_nodes[k] >= g->n) return fail(IMS_E_SEED_RANGE, "set %u: node %u >= n = %lld", i, set_nodes[k], (long long)g->n);
+            nodes.push_back(set_nodes[k]);
+        }
+        std::sort(nodes.begin() + b, nodes.end());
+        nodes.erase(std::unique(nodes.begin() + b, nodes.end()), nodes.end());
+        off.push_back((uint32_t)nodes.size());
+    }
+    const uint64_t n = (uint64_t)g->n;
+    const uint64_t tasks = (uint64_t)n_sets * W;
+    const int per_cu = opts && opts->blocks_per_cu > 0 ? opts->blocks_per_cu : 2;
+    const uint64_t slots = std::min<uint64_t>(tasks, (uint64_t)g->cus * per_cu);
+    const uint64_t cells = slots * n;
+    if ((rc = ensure_buf(g, g->sA, cells * 8, false))) return rc;
+    if ((rc = ensure_buf(g, g->sact, cells * 4, false))) return rc;
+    if ((rc = ensure_buf(g, g->sQ[0], cells * 4, false))) return rc;
+    if ((rc = ensure_buf(g, g->sQ[1], cells * 4, false))) return rc;
+    const uint64_t before = g->sN.bytes + g->sstamp.bytes + g->ssteps.bytes;
+    if (g->model == IMS_MODEL_IC) {
+        if ((rc = ensure_buf(g, g->sN, cells * 8, false))) return rc;
+        if ((rc = ensure_buf(g, g->sQ[2], cells * 16, false))) return rc;
+    } else {
+        if ((rc = ensure_buf(g, g->sQ[2], cells * 4, false))) return rc;
+        if ((rc = ensure_buf(g, g->sstamp, cells * 4, false))) return rc;
+        if ((rc = ensure_buf(g, g->ssteps, slots * 4, false))) return rc;
+    }
+    if (g->sN.bytes + g->sstamp.bytes + g->ssteps.bytes != before) g->sets_zero_dirty = true;
+    const uint64_t set_bytes = (off.size() + nodes.size()) * sizeof(uint32_t);
+    if ((rc = ensure_buf(g, g->sets_dev, set_bytes, false))) return rc;
+    uint32_t* d_off = (uint32_t*)g->sets_dev.p;
+    uint32_t* d_nodes = d_off + off.size();
+    IMS_HIP(hipMemcpyAsync(d_off, off.data(), off.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    if (!nodes.empty()) IMS_HIP(hipMemcpyAsync(d_nodes, nodes.data(), nodes.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+
+    // slot state starts clear; tasks clear what they touch
+    if ((rc = fill_async<uint64_t>((uint64_t*)g->sA.p, cells, 0ull, s))) return rc;
+    if (g->sets_zero_dirty) {
+        for (ims_graph::Buf* b : {&g->sN, &g->sstamp, &g->ssteps})
+            if (b->p && (rc = fill_async<uint8_t>((uint8_t*)b->p, b->bytes, 0, s))) return rc;
+        g->sets_zero_dirty = false;
+    }
+    if (!g->h_flag) IMS_HIP(hipHostMalloc((void**)&g->h_flag, 4 * sizeof(uint32_t), hipHostMallocDefault));
+    if ((rc = fill_async<uint32_t>(g->d_status, 4, 0u, s))) return rc;
+    if ((rc = fill_async<unsigned long long>((unsigned long long*)totals, n_sets, 0ull, s))) return rc;
+    if (node_counts && (rc = fill_async<uint32_t>(node_counts, (uint64_t)n_sets * n, 0u, s))) return rc;
+
+    imsim::SimParams P;
+    std::memset(&P, 0, sizeof P);
+    P.n = g->n;
+    P.T = n_trials;
+    P.W = W;
+    P.seed = rng_seed;
+    P.off = g->d_off;
+    P.idx = g->d_idx;
+    P.thr = g->d_thr;
+    P.in_off = g->d_in_off;
+    P.in_arc = g->d_in_arc;
+    P.in_src32 = g->d_in_src32;
+    P.node_w = g->d_node_w;
+    P.lt_uniform = g->lt_uniform ? 1 : 0;
+    P.A = (uint64_t*)g->sA.p;
+    P.N[0] = (uint64_t*)g->sN.p;
+    for (int i = 0; i < 3; ++i) P.Q[i] = (uint64_t*)g->sQ[i].p;
+    P.set_off = d_off;
+    P.set_nodes = d_nodes;
+    P.n_sets = n_sets;
+    P.totals = totals;
+    P.set_node_counts = node_counts;
+    P.act = (uint32_t*)g->sact.p;
+    P.sstamp = (uint32_t*)g->sstamp.p;
+    P.slot_steps = (uint32_t*)g->ssteps.p;
+    P.task_counter = g->d_status + 2;
+    P.status = g->d_status;
+    P.cap = g->cap;
+    if (g->model == IMS_MODEL_IC)
+        hipLaunchKernelGGL(imsim::word_ic_kernel<true>, dim3((uint32_t)slots), dim3(imsim::kBlock), 0, s, P, n);
+    else
+        hipLaunchKernelGGL(imsim::word_lt_kernel<true>, dim3((uint32_t)slots), dim3(imsim::kBlock), 0, s, P, n);
+    IMS_HIP(hipGetLastError());
     return IMS_OK;
 }
 

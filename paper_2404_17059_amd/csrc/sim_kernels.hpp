@@ -90,7 +90,16 @@ struct SimParams {
     const uint32_t* seeds;
     uint32_t n_seeds;
     uint64_t seed_arcs;  // out-arcs of the seeds (predicts the first sweep's changes)
-    uint32_t* task_counter;  // word-local: next word to take
+    uint32_t* task_counter;  // word-local: next task to take
+    // sets mode: set i's nodes are set_nodes[set_off[i] .. set_off[i+1])
+    const uint32_t* set_off;
+    const uint32_t* set_nodes;
+    uint32_t n_sets;
+    uint64_t* totals;           // [n_sets] sum over trials of active nodes
+    uint32_t* set_node_counts;  // [n_sets][n] or null
+    uint32_t* act;              // per slot: activated nodes of the current task
+    uint32_t* sstamp;           // per slot: LT candidate stamps (only grow)
+    uint32_t* slot_steps;       // per slot: last LT stamp value used
     uint32_t* status;        // [0] max steps over words, [1] guard fired
     uint32_t cap;            // step guard
 };
@@ -299,11 +308,10 @@ __device__ __forceinline__ void lt_decide(const SimParams& P, uint32_t w, uint32
 // consumed.  Each chunk is written to the wavefront's LDS slots, then every
 // lane walks it adding the weight of each arc whose source is active in its
 // trial.
-__device__ __forceinline__ void lt_eval8_core(const SimParams& P, uint32_t w, uint32_t lane, uint64_t myv, uint64_t pl,
-                                              int64_t kb, uint32_t dg, uint64_t joined[8], ArcStage* stage)
+__device__ __forceinline__ void lt_eval8_core(const SimParams& P, uint64_t* Aw, uint32_t w, uint32_t lane, uint64_t myv,
+                                              uint64_t pl, int64_t kb, uint32_t dg, uint64_t joined[8], ArcStage* stage)
 {
     const uint64_t n = (uint64_t)P.n;
-    uint64_t* Aw = P.A + (uint64_t)w * n;
     if (lane >= 8) {
         pl = 0;
         dg = 0;
@@ -431,20 +439,23 @@ __device__ __forceinline__ void lt_eval8_core(const SimParams& P, uint32_t w, ui
     }
 }
 
-// LT evaluation of nodes vs[0..7] (ids >= n are absent) for callers that hold
-// node ids only; `mark`/`min_mark` optionally restrict it to marked nodes.
-__device__ __forceinline__ void lt_eval8(const SimParams& P, uint32_t w, const uint64_t vs[8], uint32_t lane,
-                                         uint64_t joined[8], ArcStage* stage, const uint32_t* mark, uint32_t min_mark)
+// LT evaluation of nodes vs[0..7] (ids >= n are absent) of word w against
+// the word's state row Aw.  first[j] is set when node j had no active trial
+// before and joined now.
+__device__ __forceinline__ void lt_eval8(const SimParams& P, uint64_t* Aw, uint32_t w, const uint64_t vs[8], uint32_t lane,
+                                         uint64_t joined[8], bool first[8], ArcStage* stage)
 {
     const uint64_t n = (uint64_t)P.n;
     const uint64_t vm = valid_mask(w, P.W, P.T);
     const uint64_t myv = lane < 8 ? select8(vs, lane) : ~0ull;
     const bool okv = myv < n;
-    uint64_t pl = okv ? (vm & ~load_relaxed(&P.A[(uint64_t)w * n + myv])) : 0ull;
-    if (okv && pl && mark && mark[(uint64_t)w * n + myv] < min_mark) pl = 0;
+    const uint64_t pl = okv ? (vm & ~load_relaxed(&Aw[myv])) : 0ull;
     const int64_t kb = pl ? P.in_off[myv] : 0;
     const uint32_t dg = pl ? (uint32_t)(P.in_off[myv + 1] - kb) : 0u;
-    lt_eval8_core(P, w, lane, myv, pl, kb, dg, joined, stage);
+    lt_eval8_core(P, Aw, w, lane, myv, pl, kb, dg, joined, stage);
+    const uint64_t was_empty = __ballot(okv && pl == vm);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) first[j] = joined[j] != 0 && ((was_empty >> j) & 1ull);
 }
 
 // =========================================================== grid shape
@@ -900,46 +911,109 @@ __global__ __launch_bounds__(kBlock) void ltg_to_word_major(const uint64_t* __re
 }
 
 // ====================================================== word-local shape
+//
+// One workgroup runs the whole cascade of one task with workgroup barriers
+// between steps; workgroups take tasks from a counter and never wait for each
+// other.  Single-set mode: task = 64-trial word w, state rows indexed by w.
+// Sets mode (many seed sets on one graph, same rng_seed and trials): task =
+// (set, word), state rows indexed by the workgroup's slot; the activated
+// nodes of a task are listed so that its total can be counted and its state
+// cleared sparsely before the slot's next task.
 
-// Word-local IC.  Workgroups take words from a counter.  Per word: a frontier
-// list of nodes with their masks (Q[0]/Q[1] hold node ids, aux holds the
-// matching masks as uint64 pairs of uint32), a scratch mask array N[0] that is
-// zero between steps.  Step: every wavefront takes frontier entries and walks
-// their out-arcs lane-strided; a node's first new bit of the step appends it to
-// the next list (counter in LDS); after a barrier the next list picks up its
-// masks from N[0] and clears them.
+struct TaskView {
+    uint32_t set, w;
+    uint64_t slot;
+    const uint32_t* seeds;
+    uint32_t n_seeds;
+};
+
+template <bool kSets>
+__device__ __forceinline__ TaskView task_view(const SimParams& P, uint32_t t)
+{
+    TaskView v;
+    if (kSets) {
+        v.set = t / P.W;
+        v.w = t % P.W;
+        v.slot = blockIdx.x;
+        const uint32_t b = P.set_off[v.set];
+        v.seeds = P.set_nodes + b;
+        v.n_seeds = P.set_off[v.set + 1] - b;
+    } else {
+        v.set = 0;
+        v.w = t;
+        v.slot = t;
+        v.seeds = P.seeds;
+        v.n_seeds = P.n_seeds;
+    }
+    return v;
+}
+
+// Sets mode, after a task: add the task's active (node, trial) pairs to
+// totals[set] (and per-node counts when requested) and clear its state rows.
+__device__ __forceinline__ void finish_set_task(const SimParams& P, const TaskView& tv, uint64_t* Aw, const uint32_t* act,
+                                                uint32_t n_act, unsigned long long* s_total)
+{
+    unsigned long long mine = 0;
+    for (uint32_t i = threadIdx.x; i < n_act; i += kBlock) {
+        const uint32_t v = act[i];
+        const uint32_t c = (uint32_t)__popcll(Aw[v]);
+        mine += c;
+        if (P.set_node_counts) atomicAdd(&P.set_node_counts[(uint64_t)tv.set * (uint64_t)P.n + v], c);
+        Aw[v] = 0;
+    }
+    for (int o = 32; o > 0; o >>= 1) mine += __shfl_down(mine, o);
+    if ((threadIdx.x & 63u) == 0 && mine) atomicAdd(s_total, mine);
+    __syncthreads();
+    if (threadIdx.x == 0 && *s_total) atomicAdd((unsigned long long*)&P.totals[tv.set], *s_total);
+}
+
+// Word-local IC.  Per task: a frontier list of nodes with their masks (node
+// ids in Q[0]/Q[1], masks in Q[2]) and a scratch mask row N[0] that is zero
+// between steps.  Step: every wavefront takes frontier entries and walks their
+// out-arcs lane-strided; a node's first new bit of the step appends it to the
+// next list (counter in LDS); after a barrier the next list picks up its masks
+// from N[0] and clears them.
+template <bool kSets>
 __global__ __launch_bounds__(kBlock) void word_ic_kernel(SimParams P, uint64_t list_cap)
 {
-    __shared__ uint32_t s_word;
+    __shared__ uint32_t s_task;
     __shared__ uint32_t s_cnt[2];
     __shared__ uint32_t s_next_item;
+    __shared__ uint32_t s_act;
+    __shared__ unsigned long long s_total;
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t n = (uint64_t)P.n;
+    const uint32_t n_tasks = kSets ? P.n_sets * P.W : P.W;
     uint32_t max_steps = 0;
     bool guard = false;
     for (;;) {
         __syncthreads();
-        if (threadIdx.x == 0) s_word = atomicAdd(P.task_counter, 1u);
+        if (threadIdx.x == 0) s_task = atomicAdd(P.task_counter, 1u);
         __syncthreads();
-        const uint32_t w = s_word;
-        if (w >= P.W) break;
+        const uint32_t t = s_task;
+        if (t >= n_tasks) break;
+        const TaskView tv = task_view<kSets>(P, t);
+        const uint32_t w = tv.w;
         const uint64_t vm = valid_mask(w, P.W, P.T);
-        uint64_t* Aw = P.A + (uint64_t)w * n;
-        uint64_t* Nw = P.N[0] + (uint64_t)w * n;
-        // per-word lists: node ids in Q[0]/Q[1] (as uint32), masks in aux (as uint64)
-        uint32_t* L[2] = {(uint32_t*)P.Q[0] + (uint64_t)w * list_cap, (uint32_t*)P.Q[1] + (uint64_t)w * list_cap};
-        uint64_t* M[2] = {(uint64_t*)P.Q[2] + (uint64_t)w * list_cap * 2, (uint64_t*)P.Q[2] + (uint64_t)w * list_cap * 2 + list_cap};
+        uint64_t* Aw = P.A + tv.slot * n;
+        uint64_t* Nw = P.N[0] + tv.slot * n;
+        uint32_t* L[2] = {(uint32_t*)P.Q[0] + tv.slot * list_cap, (uint32_t*)P.Q[1] + tv.slot * list_cap};
+        uint64_t* M[2] = {(uint64_t*)P.Q[2] + tv.slot * list_cap * 2, (uint64_t*)P.Q[2] + tv.slot * list_cap * 2 + list_cap};
+        uint32_t* act = kSets ? P.act + tv.slot * n : nullptr;
         if (threadIdx.x == 0) {
             s_cnt[0] = 0;
             s_cnt[1] = 0;
+            s_act = 0;
+            s_total = 0;
         }
         __syncthreads();
-        for (uint32_t i = threadIdx.x; i < P.n_seeds; i += kBlock) {
-            const uint32_t s = P.seeds[i];
-            Aw[s] = vm;
-            if (P.off[s + 1] > P.off[s]) {
+        for (uint32_t i = threadIdx.x; i < tv.n_seeds; i += kBlock) {
+            const uint32_t sd = tv.seeds[i];
+            Aw[sd] = vm;
+            if (kSets) act[atomicAdd(&s_act, 1u)] = sd;
+            if (P.off[sd + 1] > P.off[sd]) {
                 const uint32_t pos = atomicAdd(&s_cnt[0], 1u);
-                L[0][pos] = s;
+                L[0][pos] = sd;
                 M[0][pos] = vm;
             }
         }
@@ -976,7 +1050,9 @@ __global__ __launch_bounds__(kBlock) void word_ic_kernel(SimParams P, uint64_t l
                     if (todo == 0) continue;
                     const uint64_t live = ic_live(todo, th, (uint64_t)e, w, P.seed);
                     if (live == 0) continue;
-                    const uint64_t fresh = live & ~atomic_or64(&Aw[v], live);
+                    const uint64_t old = atomic_or64(&Aw[v], live);
+                    const uint64_t fresh = live & ~old;
+                    if (kSets && old == 0) act[atomicAdd(&s_act, 1u)] = v;
                     if (fresh == 0 || P.off[v + 1] == P.off[v]) continue;
                     if (atomic_or64(&Nw[v], fresh) == 0) {
                         const uint32_t pos = atomicAdd(&s_cnt[nxt], 1u);
@@ -994,6 +1070,7 @@ __global__ __launch_bounds__(kBlock) void word_ic_kernel(SimParams P, uint64_t l
             __syncthreads();
             cur = nxt;
         }
+        if (kSets) finish_set_task(P, tv, Aw, act, s_act, &s_total);
         max_steps = steps > max_steps ? steps : max_steps;
     }
     if (threadIdx.x == 0) {
@@ -1002,43 +1079,58 @@ __global__ __launch_bounds__(kBlock) void word_ic_kernel(SimParams P, uint64_t l
     }
 }
 
-// Word-local LT.  Per word: the frontier list holds the nodes that joined in
+// Word-local LT.  Per task: the frontier list holds the nodes that joined in
 // the previous step (any trial); their out-neighbours with an inactive trial
-// are collected once each (stamp per node in aux) into a candidate list, then
-// wavefronts evaluate candidates eight at a time; nodes that joined form the
-// next frontier.
+// are collected once each into a candidate list (a per-node stamp records the
+// last step that collected it), then wavefronts evaluate candidates eight at
+// a time; nodes that joined form the next frontier.  Single-set mode clears
+// its stamps at the end of the word; sets mode numbers steps with a per-slot
+// counter that only grows, so old stamps never match.
+template <bool kSets>
 __global__ __launch_bounds__(kBlock) void word_lt_kernel(SimParams P, uint64_t list_cap)
 {
     __shared__ ArcStage stage[kWaves][64];
-    __shared__ uint32_t s_word;
+    __shared__ uint32_t s_task;
     __shared__ uint32_t s_cnt[2];
     __shared__ uint32_t s_cand;
     __shared__ uint32_t s_next_item;
+    __shared__ uint32_t s_act;
+    __shared__ uint32_t s_base;
+    __shared__ unsigned long long s_total;
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t n = (uint64_t)P.n;
+    const uint32_t n_tasks = kSets ? P.n_sets * P.W : P.W;
     uint32_t max_steps = 0;
     bool guard = false;
     for (;;) {
         __syncthreads();
-        if (threadIdx.x == 0) s_word = atomicAdd(P.task_counter, 1u);
+        if (threadIdx.x == 0) s_task = atomicAdd(P.task_counter, 1u);
         __syncthreads();
-        const uint32_t w = s_word;
-        if (w >= P.W) break;
+        const uint32_t t = s_task;
+        if (t >= n_tasks) break;
+        const TaskView tv = task_view<kSets>(P, t);
+        const uint32_t w = tv.w;
         const uint64_t vm = valid_mask(w, P.W, P.T);
-        uint64_t* Aw = P.A + (uint64_t)w * n;
-        uint32_t* stamp = P.aux + (uint64_t)w * n;  // last step in which v became a candidate
-        uint32_t* F[2] = {(uint32_t*)P.Q[0] + (uint64_t)w * list_cap, (uint32_t*)P.Q[1] + (uint64_t)w * list_cap};
-        uint32_t* C = (uint32_t*)P.Q[2] + (uint64_t)w * list_cap;
+        uint64_t* Aw = P.A + tv.slot * n;
+        uint32_t* stamp = (kSets ? P.sstamp : P.aux) + tv.slot * n;
+        uint32_t* F[2] = {(uint32_t*)P.Q[0] + tv.slot * list_cap, (uint32_t*)P.Q[1] + tv.slot * list_cap};
+        uint32_t* C = (uint32_t*)P.Q[2] + tv.slot * list_cap;
+        uint32_t* act = kSets ? P.act + tv.slot * n : nullptr;
         if (threadIdx.x == 0) {
             s_cnt[0] = 0;
             s_cnt[1] = 0;
+            s_act = 0;
+            s_total = 0;
+            s_base = kSets ? P.slot_steps[tv.slot] : 0u;
         }
         __syncthreads();
-        for (uint32_t i = threadIdx.x; i < P.n_seeds; i += kBlock) {
-            const uint32_t s = P.seeds[i];
-            Aw[s] = vm;
+        const uint32_t base = s_base;
+        for (uint32_t i = threadIdx.x; i < tv.n_seeds; i += kBlock) {
+            const uint32_t sd = tv.seeds[i];
+            Aw[sd] = vm;
             const uint32_t pos = atomicAdd(&s_cnt[0], 1u);
-            F[0][pos] = s;
+            F[0][pos] = sd;
+            if (kSets) act[atomicAdd(&s_act, 1u)] = sd;
         }
         __syncthreads();
         uint32_t cur = 0, steps = 0;
@@ -1050,6 +1142,7 @@ __global__ __launch_bounds__(kBlock) void word_lt_kernel(SimParams P, uint64_t l
                 break;
             }
             ++steps;
+            const uint32_t mark = base + steps;
             const uint32_t nxt = cur ^ 1u;
             if (threadIdx.x == 0) {
                 s_cnt[nxt] = 0;
@@ -1068,7 +1161,7 @@ __global__ __launch_bounds__(kBlock) void word_lt_kernel(SimParams P, uint64_t l
                 for (int64_t e = P.off[u] + lane; e < e1; e += 64) {
                     const uint32_t v = P.idx[e];
                     if ((vm & ~Aw[v]) == 0) continue;
-                    if (atomicMax(&stamp[v], steps) < steps) {
+                    if (atomicMax(&stamp[v], mark) < mark) {
                         const uint32_t pos = atomicAdd(&s_cand, 1u);
                         C[pos] = v;
                     }
@@ -1085,22 +1178,29 @@ __global__ __launch_bounds__(kBlock) void word_lt_kernel(SimParams P, uint64_t l
                 it = __shfl(it, 0);
                 if (it >= ncand) break;
                 uint64_t vs[8], joined[8];
+                bool first[8];
 #pragma unroll
                 for (int j = 0; j < 8; ++j) vs[j] = it + j < ncand ? (uint64_t)C[it + j] : ~0ull;
-                lt_eval8(P, w, vs, lane, joined, stage[threadIdx.x >> 6], nullptr, 0);
+                lt_eval8(P, Aw, w, vs, lane, joined, first, stage[threadIdx.x >> 6]);
 #pragma unroll
                 for (int j = 0; j < 8; ++j)
                     if (joined[j] && lane == 0) {
                         const uint32_t pos = atomicAdd(&s_cnt[nxt], 1u);
                         F[nxt][pos] = (uint32_t)vs[j];
+                        if (kSets && first[j]) act[atomicAdd(&s_act, 1u)] = (uint32_t)vs[j];
                     }
             }
             __syncthreads();
             cur = nxt;
         }
-        // clear this word's stamps for the next run
         __syncthreads();
-        for (uint64_t v = threadIdx.x; v < n; v += kBlock) stamp[v] = 0;
+        if (kSets) {
+            if (threadIdx.x == 0) P.slot_steps[tv.slot] = base + steps + 1;
+            finish_set_task(P, tv, Aw, act, s_act, &s_total);
+        } else {
+            // clear this word's stamps for the next run
+            for (uint64_t v = threadIdx.x; v < n; v += kBlock) stamp[v] = 0;
+        }
         max_steps = steps > max_steps ? steps : max_steps;
     }
     if (threadIdx.x == 0) {

@@ -184,3 +184,58 @@ def test_lt_grid_threshold_paths_and_direction_switch(ims, flags, alpha):
     seeds = synth.top_outdeg_seeds(g, 20)
     opts = ims.Opts(shape=2, blocks_per_cu=0, alpha=alpha, profile=0, test_flags=flags)
     run_both(ims, "lt", g.n, g.offsets, g.indices, param, seeds, 200, 23, opts=opts)
+
+
+@pytest.mark.parametrize("model", ["ic", "lt"])
+def test_sets_equal_single_runs_and_oracle(ims, model):
+    """Many seed sets at once (common random numbers) == each set alone."""
+    g = synth.barabasi_albert(2000, 3, seed=21)
+    param = synth.weighted_cascade(g)
+    rng = np.random.default_rng(5)
+    sets = [rng.choice(g.n, size=int(rng.integers(0, 6)), replace=True).astype(np.uint32) for _ in range(37)]
+    sets[3] = np.array([], np.uint32)
+    sets[4] = np.array([7, 7, 7], np.uint32)
+    T, rs = 130, 77
+    say(f"[parity] sets model={model} n_sets={len(sets)} T={T}")
+    G = ims.Graph(g.n, g.offsets, g.indices, model, param)
+    got = ims.simulate_sets(G, sets, T, rs, want_node_counts=True)
+    enc = oracle.encode(model, param)
+    for i, st in enumerate(sets):
+        ref = oracle.simulate(model, g.n, g.offsets, g.indices, enc, st, T, rs, want_bits=False)
+        assert int(got["totals"][i]) == ref["total"], i
+        assert (got["node_counts"][i] == ref["node_counts"]).all(), i
+    # a second call on the same handle (slot state reused) gives the same
+    again = ims.simulate_sets(G, sets[::-1], T, rs)
+    assert (again["totals"] == got["totals"][::-1]).all()
+    G.close()
+
+
+def test_celf_equals_greedy_and_oracle_greedy(ims):
+    """CELF on sigma with common random numbers returns exactly the plain
+    greedy picks (submodular coverage), and the plain greedy equals a greedy
+    computed from oracle spreads."""
+    from paper_2404_17059_amd import im
+    g = synth.random_regular(300, 4, seed=8)
+    param = synth.weighted_cascade(g)
+    G = ims.Graph(g.n, g.offsets, g.indices, "ic", param)
+    R, rs, k = 256, 9, 4
+    a = im.celf(G, k, R, rs)
+    b = im.greedy(G, k, R, rs)
+    assert a["seeds"] == b["seeds"]
+    assert a["sigma"] == b["sigma"]
+    # oracle greedy
+    enc = oracle.encode("ic", param)
+    S = []
+    for _ in range(k):
+        best, best_t = None, -1
+        for v in range(g.n):
+            if v in S:
+                continue
+            t = oracle.simulate("ic", g.n, g.offsets, g.indices, enc, S + [v], R, rs, want_bits=False,
+                                want_node_counts=False, threads=8)["total"]
+            if t > best_t:
+                best, best_t = v, t
+        S.append(best)
+    assert S == a["seeds"]
+    assert a["evaluations"] < b["evaluations"]
+    G.close()
