@@ -138,6 +138,40 @@ int ims_simulate_sets(ims_graph* g, const uint32_t* set_offsets, const uint32_t*
                       uint32_t n_trials, uint64_t rng_seed, const ims_opts* opts, uint64_t* totals,
                       uint32_t* node_counts, void* stream);
 
+/* Batch: several (graph, seeds, trials, rng_seed) runs, IC and LT mixed,
+ * executed by one persistent launch that takes (item, 64-trial word) tasks
+ * in a scheduled order, captured once in a HIP graph and replayed.  Each
+ * item's outputs equal those of ims_simulate on that item alone. */
+typedef struct ims_batch ims_batch;
+
+typedef struct ims_batch_item {
+    ims_graph* graph;        /* not owned; must outlive the batch */
+    const uint32_t* seeds;   /* host; copied at creation */
+    uint32_t n_seeds;
+    uint32_t n_trials;       /* 1 .. 2^18 */
+    uint64_t rng_seed;
+    uint32_t* trial_counts;  /* device uint32[n_trials], required */
+    uint32_t* node_counts;   /* device uint32[n] or NULL */
+    uint64_t* total;         /* device uint64[1], required */
+} ims_batch_item;
+
+typedef struct ims_tuning {
+    int32_t blocks_per_cu;  /* persistent workgroups per compute unit (1..16) */
+    int32_t order;          /* 0 = items by estimated cost, largest first; 1 = item order */
+} ims_tuning;
+
+/* tuning NULL = defaults (2 per CU, largest first).  Synchronous. */
+int ims_batch_create(const ims_batch_item* items, uint32_t n_items, const ims_tuning* tuning, ims_batch** out);
+/* Time every candidate schedule `repeats` times on `stream`, check that all
+ * give identical outputs, keep the fastest (reported in *chosen if not NULL)
+ * and drop the captured graph.  Synchronous. */
+int ims_batch_autotune(ims_batch* b, int repeats, void* stream, ims_tuning* chosen);
+/* Run the batch on `stream`: the first call (and the first after a tuning
+ * change) captures the launch sequence into a HIP graph, later calls replay
+ * it.  Asynchronous. */
+int ims_batch_launch(ims_batch* b, void* stream);
+int ims_batch_destroy(ims_batch* b);
+
 /* Status of the last run on this handle: out[0] = steps (IC frontier levels
  * or LT sweeps) taken, out[1] = nonzero if the step guard fired.  Waits for
  * `stream`. */

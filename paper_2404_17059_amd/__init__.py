@@ -38,6 +38,16 @@ class Opts(ctypes.Structure):
                 ("profile", ctypes.c_int32), ("test_flags", ctypes.c_int32)]
 
 
+class BatchItem(ctypes.Structure):
+    _fields_ = [("graph", ctypes.c_void_p), ("seeds", ctypes.c_void_p), ("n_seeds", ctypes.c_uint32),
+                ("n_trials", ctypes.c_uint32), ("rng_seed", ctypes.c_uint64), ("trial_counts", ctypes.c_void_p),
+                ("node_counts", ctypes.c_void_p), ("total", ctypes.c_void_p)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("blocks_per_cu", ctypes.c_int32), ("order", ctypes.c_int32)]
+
+
 def _sig(name, res, *args):
     f = getattr(_lib, name)
     f.restype = res
@@ -55,6 +65,10 @@ _sig("ims_graph_destroy", _int, _P)
 _sig("ims_graph_info", _int, _P, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_int))
 _sig("ims_simulate", _int, _P, _P, _u32, _u32, _u64, ctypes.POINTER(Opts), _P, _P, _P, _P, _P)
 _sig("ims_graph_last_status", _int, _P, _P, _P)
+_sig("ims_batch_create", _int, ctypes.POINTER(BatchItem), _u32, ctypes.POINTER(Tuning), ctypes.POINTER(_P))
+_sig("ims_batch_autotune", _int, _P, _int, _P, ctypes.POINTER(Tuning))
+_sig("ims_batch_launch", _int, _P, _P)
+_sig("ims_batch_destroy", _int, _P)
 _sig("ims_simulate_sets", _int, _P, _P, _P, _u32, _u32, _u64, ctypes.POINTER(Opts), _P, _P, _P)
 _sig("ims_graph_profile", _int, _P, _int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_u32))
 _sig("ims_debug_hash", _int, _u64, _u64, _P, _P, _P, _i64, _P)
@@ -238,6 +252,63 @@ def simulate_sets(graph: Graph, sets, n_trials: int, rng_seed: int, want_node_co
     if want_node_counts:
         out["node_counts"] = nc.cpu().numpy().view(np.uint32)[:n_sets]
     return out
+
+
+class Batch:
+    """Several simulations (IC and LT, graphs of any size) run by one
+    persistent launch; the first launch captures a HIP graph that later
+    launches replay.  items: (Graph, seeds, n_trials, rng_seed) tuples."""
+
+    def __init__(self, items, tuning: tuple[int, int] | None = None, want_node_counts: bool = True):
+        torch = _torch()
+        dev = torch.device("cuda", torch.cuda.current_device())
+        self.graphs = [it[0] for it in items]
+        self.outputs = []
+        arr = (BatchItem * max(len(items), 1))()
+        keep = []
+        for i, (g, seeds, T, rs) in enumerate(items):
+            sd = np.ascontiguousarray(seeds, dtype=np.uint32)
+            keep.append(sd)
+            tc = torch.empty(int(T), dtype=torch.int32, device=dev)
+            nc = torch.empty(g.n, dtype=torch.int32, device=dev) if want_node_counts else None
+            tot = torch.empty(1, dtype=torch.int64, device=dev)
+            self.outputs.append((tc, nc, tot, int(T)))
+            arr[i] = BatchItem(g.handle.value, sd.ctypes.data if sd.size else None, sd.shape[0], int(T),
+                               int(rs) & ((1 << 64) - 1), tc.data_ptr(), nc.data_ptr() if nc is not None else None,
+                               tot.data_ptr())
+        tun = Tuning(*tuning) if tuning is not None else None
+        h = ctypes.c_void_p()
+        _check(_lib.ims_batch_create(arr, len(items), ctypes.byref(tun) if tun is not None else None, ctypes.byref(h)),
+               "ims_batch_create")
+        self._h = h
+
+    def autotune(self, repeats: int = 2, stream=None) -> tuple[int, int]:
+        t = Tuning()
+        _check(_lib.ims_batch_autotune(self._h, int(repeats), _stream_handle(stream), ctypes.byref(t)), "ims_batch_autotune")
+        return int(t.blocks_per_cu), int(t.order)
+
+    def launch(self, stream=None) -> None:
+        _check(_lib.ims_batch_launch(self._h, _stream_handle(stream)), "ims_batch_launch")
+
+    def results(self) -> list[dict]:
+        out = []
+        for tc, nc, tot, T in self.outputs:
+            total = int(tot.item())
+            out.append({"trial_counts": tc.cpu().numpy().view(np.uint32),
+                        "node_counts": None if nc is None else nc.cpu().numpy().view(np.uint32),
+                        "total": total, "mean": total / T})
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.ims_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def debug_hash(rng_seed: int, domain: int, trials, ids) -> np.ndarray:

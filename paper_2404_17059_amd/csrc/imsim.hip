@@ -512,9 +512,9 @@ int ims_simulate(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_t
         const int per_cu = opts && opts->blocks_per_cu > 0 ? opts->blocks_per_cu : 2;
         const uint32_t blocks = std::min<uint32_t>(W, (uint32_t)(g->cus * per_cu));
         if (g->model == IMS_MODEL_IC)
-            hipLaunchKernelGGL(imsim::word_ic_kernel<false>, dim3(blocks), dim3(imsim::kBlock), 0, s, P, n);
+            hipLaunchKernelGGL((imsim::word_kernel<false, false>), dim3(blocks), dim3(imsim::kTaskBlock), 0, s, P, n);
         else
-            hipLaunchKernelGGL(imsim::word_lt_kernel<false>, dim3(blocks), dim3(imsim::kBlock), 0, s, P, n);
+            hipLaunchKernelGGL((imsim::word_kernel<false, true>), dim3(blocks), dim3(imsim::kTaskBlock), 0, s, P, n);
         IMS_HIP(hipGetLastError());
     } else {
         const int per_cu = opts && opts->blocks_per_cu > 0 ? opts->blocks_per_cu : 8;
@@ -706,10 +706,269 @@ int ims_simulate_sets(ims_graph* g, const uint32_t* set_offsets, const uint32_t*
     P.status = g->d_status;
     P.cap = g->cap;
     if (g->model == IMS_MODEL_IC)
-        hipLaunchKernelGGL(imsim::word_ic_kernel<true>, dim3((uint32_t)slots), dim3(imsim::kBlock), 0, s, P, n);
+        hipLaunchKernelGGL((imsim::word_kernel<true, false>), dim3((uint32_t)slots), dim3(imsim::kTaskBlock), 0, s, P, n);
     else
-        hipLaunchKernelGGL(imsim::word_lt_kernel<true>, dim3((uint32_t)slots), dim3(imsim::kBlock), 0, s, P, n);
+        hipLaunchKernelGGL((imsim::word_kernel<true, true>), dim3((uint32_t)slots), dim3(imsim::kTaskBlock), 0, s, P, n);
     IMS_HIP(hipGetLastError());
+    return IMS_OK;
+}
+
+}  // extern "C"
+
+struct ims_batch {
+    std::vector<ims_batch_item> items;
+    std::vector<imsim::BatchItem> host_items;
+    std::vector<uint32_t*> dev_seeds;
+    std::vector<double> cost;
+    ims_tuning tuning{2, 0};
+    int device = 0, cus = 0;
+    uint64_t max_n = 1;
+    uint32_t n_tasks = 0;
+    imsim::BatchItem* d_items = nullptr;
+    uint32_t* d_tasks = nullptr;
+    uint32_t* d_ctl = nullptr;  // [0] task counter, [1..2] status
+    ims_graph::Buf sA, sN, sQ0, sQ1, sQ2, sact, sstamp, ssteps;
+    uint32_t slots = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t capture_stream = nullptr;  // the null stream cannot be captured
+
+    void drop_graph()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    }
+    ~ims_batch()
+    {
+        drop_graph();
+        if (capture_stream) (void)hipStreamDestroy(capture_stream);
+        for (auto* p : dev_seeds) dev_free(p);
+        dev_free(d_items);
+        dev_free(d_tasks);
+        dev_free(d_ctl);
+        for (ims_graph::Buf* b : {&sA, &sN, &sQ0, &sQ1, &sQ2, &sact, &sstamp, &ssteps}) ims_graph::release(*b);
+    }
+};
+
+namespace {
+
+// Grow a batch buffer; fresh buffers are zero-filled (slot rows, next-step
+// masks and stamps must start clear; tasks leave them clear).
+int batch_buf(ims_graph::Buf& b, uint64_t bytes)
+{
+    if (b.p && b.bytes >= bytes) return IMS_OK;
+    ims_graph::release(b);
+    uint8_t* p = nullptr;
+    int rc = dev_alloc(&p, std::max<uint64_t>(bytes, 8));
+    if (rc) return rc;
+    b.p = p;
+    b.bytes = std::max<uint64_t>(bytes, 8);
+    IMS_HIP(hipMemset(p, 0, b.bytes));
+    return IMS_OK;
+}
+
+// Task list and slot state for the current tuning.
+int batch_plan(ims_batch* b)
+{
+    const uint32_t n_items = (uint32_t)b->items.size();
+    std::vector<uint32_t> order(n_items);
+    for (uint32_t i = 0; i < n_items; ++i) order[i] = i;
+    if (b->tuning.order == 0)
+        std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) { return b->cost[x] > b->cost[y]; });
+    std::vector<uint32_t> tasks;
+    for (uint32_t i : order)
+        for (uint32_t w = 0; w < b->host_items[i].P.W; ++w) tasks.push_back((i << 12) | w);
+    b->n_tasks = (uint32_t)tasks.size();
+    dev_free(b->d_tasks);
+    int rc = dev_alloc(&b->d_tasks, tasks.size());
+    if (rc) return rc;
+    if (!tasks.empty()) IMS_HIP(hipMemcpy(b->d_tasks, tasks.data(), tasks.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    const int per_cu = std::min(std::max(b->tuning.blocks_per_cu, 1), 16);
+    b->slots = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(b->n_tasks, (uint64_t)b->cus * per_cu));
+    const uint64_t cells = (uint64_t)b->slots * b->max_n;
+    if ((rc = batch_buf(b->sA, cells * 8)) || (rc = batch_buf(b->sN, cells * 8)) || (rc = batch_buf(b->sQ0, cells * 4)) ||
+        (rc = batch_buf(b->sQ1, cells * 4)) || (rc = batch_buf(b->sQ2, cells * 16)) || (rc = batch_buf(b->sact, cells * 4)) ||
+        (rc = batch_buf(b->sstamp, cells * 4)) || (rc = batch_buf(b->ssteps, (uint64_t)b->slots * 4)))
+        return rc;
+    b->drop_graph();
+    return IMS_OK;
+}
+
+// Enqueue one batch run: clear outputs and the task counter (fill kernels, no
+// memset nodes, so the sequence can be captured), then the persistent launch.
+int batch_enqueue(ims_batch* b, hipStream_t s)
+{
+    int rc;
+    for (const auto& it : b->items) {
+        if ((rc = fill_async<uint32_t>(it.trial_counts, it.n_trials, 0u, s))) return rc;
+        if (it.node_counts) {
+            int64_t n = 0;
+            ims_graph_info(it.graph, &n, nullptr, nullptr);
+            if ((rc = fill_async<uint32_t>(it.node_counts, (uint64_t)n, 0u, s))) return rc;
+        }
+        if ((rc = fill_async<unsigned long long>((unsigned long long*)it.total, 1, 0ull, s))) return rc;
+    }
+    if ((rc = fill_async<uint32_t>(b->d_ctl, 4, 0u, s))) return rc;
+    hipLaunchKernelGGL(imsim::batch_kernel, dim3(b->slots), dim3(imsim::kTaskBlock), 0, s, (const imsim::BatchItem*)b->d_items,
+                       (const uint32_t*)b->d_tasks, b->n_tasks, b->d_ctl, b->max_n, (uint64_t*)b->sA.p, (uint64_t*)b->sN.p,
+                       (uint32_t*)b->sQ0.p, (uint32_t*)b->sQ1.p, (uint64_t*)b->sQ2.p, (uint32_t*)b->sact.p, (uint32_t*)b->sstamp.p,
+                       (uint32_t*)b->ssteps.p, b->d_ctl + 1);
+    IMS_HIP(hipGetLastError());
+    return IMS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ims_batch_create(const ims_batch_item* items, uint32_t n_items, const ims_tuning* tuning, ims_batch** out)
+{
+    if (!out || (n_items > 0 && !items)) return fail(IMS_E_INVALID_ARG, "ims_batch_create: bad arguments");
+    *out = nullptr;
+    if (n_items >= (1u << 20)) return fail(IMS_E_UNSUPPORTED, "ims_batch_create: at most 2^20 - 1 items");
+    auto* b = new (std::nothrow) ims_batch();
+    if (!b) return fail(IMS_E_OOM, "host allocation failed");
+    auto bail = [&](int code) {
+        delete b;
+        return code;
+    };
+    (void)hipGetDevice(&b->device);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, b->device) != hipSuccess) return bail(fail(IMS_E_HIP, "hipGetDeviceProperties failed"));
+    b->cus = prop.multiProcessorCount;
+    if (tuning) b->tuning = *tuning;
+    for (uint32_t i = 0; i < n_items; ++i) {
+        const ims_batch_item& it = items[i];
+        if (!it.graph || !it.trial_counts || !it.total || it.n_trials == 0 || (it.n_seeds > 0 && !it.seeds))
+            return bail(fail(IMS_E_INVALID_ARG, "ims_batch_create: item %u incomplete", i));
+        if (it.n_trials > imsim::kMaxWords * 64u) return bail(fail(IMS_E_UNSUPPORTED, "item %u: n_trials above %u", i, imsim::kMaxWords * 64u));
+        ims_graph* g = it.graph;
+        std::vector<uint32_t> sv(it.seeds, it.seeds + it.n_seeds);
+        for (uint32_t x : sv)
+            if ((int64_t)x >= g->n) return bail(fail(IMS_E_SEED_RANGE, "item %u: seed %u >= n", i, x));
+        std::sort(sv.begin(), sv.end());
+        sv.erase(std::unique(sv.begin(), sv.end()), sv.end());
+        uint32_t* d = nullptr;
+        int rc = dev_alloc(&d, sv.size());
+        if (rc) return bail(rc);
+        b->dev_seeds.push_back(d);
+        if (!sv.empty() && hipMemcpy(d, sv.data(), sv.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+            return bail(fail(IMS_E_HIP, "seed upload failed"));
+        imsim::BatchItem bi;
+        std::memset(&bi, 0, sizeof bi);
+        imsim::SimParams& P = bi.P;
+        P.n = g->n;
+        P.T = it.n_trials;
+        P.W = (it.n_trials + 63) / 64;
+        P.seed = it.rng_seed;
+        P.off = g->d_off;
+        P.idx = g->d_idx;
+        P.thr = g->d_thr;
+        P.in_off = g->d_in_off;
+        P.in_arc = g->d_in_arc;
+        P.in_src32 = g->d_in_src32;
+        P.node_w = g->d_node_w;
+        P.lt_uniform = g->lt_uniform ? 1 : 0;
+        P.seeds = d;
+        P.n_seeds = (uint32_t)sv.size();
+        P.cap = g->cap;
+        bi.model = g->model;
+        bi.trial_counts = it.trial_counts;
+        bi.node_counts = it.node_counts;
+        bi.total = it.total;
+        b->host_items.push_back(bi);
+        b->items.push_back(it);
+        b->cost.push_back((double)P.W * (double)(g->m + g->n));
+        b->max_n = std::max<uint64_t>(b->max_n, (uint64_t)g->n);
+    }
+    int rc = dev_alloc(&b->d_items, std::max<size_t>(b->host_items.size(), 1));
+    if (rc) return bail(rc);
+    if (!b->host_items.empty() &&
+        hipMemcpy(b->d_items, b->host_items.data(), b->host_items.size() * sizeof(imsim::BatchItem), hipMemcpyHostToDevice) != hipSuccess)
+        return bail(fail(IMS_E_HIP, "item upload failed"));
+    if ((rc = dev_alloc(&b->d_ctl, 4))) return bail(rc);
+    if ((rc = batch_plan(b))) return bail(rc);
+    *out = b;
+    return IMS_OK;
+}
+
+int ims_batch_launch(ims_batch* b, void* stream)
+{
+    if (!b) return fail(IMS_E_INVALID_ARG, "ims_batch_launch: NULL batch");
+    hipStream_t s = (hipStream_t)stream;
+    if (!b->exec) {
+        // record the launch sequence on a private stream (default priority);
+        // the instantiated graph then runs on the caller's stream
+        if (!b->capture_stream) IMS_HIP(hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking));
+        hipStream_t cs = b->capture_stream;
+        IMS_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        int rc = batch_enqueue(b, cs);
+        hipGraph_t gph = nullptr;
+        hipError_t e = hipStreamEndCapture(cs, &gph);
+        if (rc) {
+            if (gph) (void)hipGraphDestroy(gph);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(IMS_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        b->graph = gph;
+        IMS_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    }
+    IMS_HIP(hipGraphLaunch(b->exec, s));
+    return IMS_OK;
+}
+
+int ims_batch_autotune(ims_batch* b, int repeats, void* stream, ims_tuning* chosen)
+{
+    if (!b || repeats < 1) return fail(IMS_E_INVALID_ARG, "ims_batch_autotune: bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    const ims_tuning cands[] = {{1, 0}, {2, 0}, {4, 0}, {8, 0}, {2, 1}, {4, 1}};
+    hipEvent_t e0, e1;
+    IMS_HIP(hipEventCreate(&e0));
+    IMS_HIP(hipEventCreate(&e1));
+    double best_ms = 1e300;
+    ims_tuning best = b->tuning;
+    std::vector<uint64_t> ref, cur(b->items.size());
+    int rc = IMS_OK;
+    for (const ims_tuning& c : cands) {
+        b->tuning = c;
+        if ((rc = batch_plan(b))) break;
+        if ((rc = batch_enqueue(b, s))) break;  // warm-up
+        IMS_HIP(hipEventRecord(e0, s));
+        for (int r = 0; r < repeats && !rc; ++r) rc = batch_enqueue(b, s);
+        if (rc) break;
+        IMS_HIP(hipEventRecord(e1, s));
+        IMS_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        IMS_HIP(hipEventElapsedTime(&ms, e0, e1));
+        for (size_t i = 0; i < b->items.size(); ++i)
+            IMS_HIP(hipMemcpy(&cur[i], b->items[i].total, sizeof(uint64_t), hipMemcpyDeviceToHost));
+        if (ref.empty()) ref = cur;
+        else if (cur != ref) {
+            rc = fail(IMS_E_HIP, "ims_batch_autotune: schedule {%d,%d} changed the results", c.blocks_per_cu, c.order);
+            break;
+        }
+        if (ms / repeats < best_ms) {
+            best_ms = ms / repeats;
+            best = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    b->tuning = best;
+    if ((rc = batch_plan(b))) return rc;
+    if (chosen) *chosen = best;
+    return IMS_OK;
+}
+
+int ims_batch_destroy(ims_batch* b)
+{
+    if (b) {
+        (void)hipDeviceSynchronize();
+        delete b;
+    }
     return IMS_OK;
 }
 

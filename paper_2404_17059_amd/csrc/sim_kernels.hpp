@@ -914,298 +914,379 @@ __global__ __launch_bounds__(kBlock) void ltg_to_word_major(const uint64_t* __re
 //
 // One workgroup runs the whole cascade of one task with workgroup barriers
 // between steps; workgroups take tasks from a counter and never wait for each
-// other.  Single-set mode: task = 64-trial word w, state rows indexed by w.
-// Sets mode (many seed sets on one graph, same rng_seed and trials): task =
-// (set, word), state rows indexed by the workgroup's slot; the activated
-// nodes of a task are listed so that its total can be counted and its state
-// cleared sparsely before the slot's next task.
+// other.  Three launch forms share the task bodies below:
+//   single set  task = 64-trial word w, state rows indexed by w;
+//   many sets   task = (set, word) on one graph (same rng_seed and trials),
+//               state rows indexed by the workgroup's slot;
+//   batch       task = (item, word) over several graphs, IC and LT mixed,
+//               state rows indexed by the workgroup's slot.
+// In the slot forms the nodes a task activates are listed, so that its
+// counts can be taken and its state cleared sparsely before the next task.
 
-struct TaskView {
-    uint32_t set, w;
-    uint64_t slot;
+constexpr int kTaskBlock = 512;  // word-local workgroup: 8 wavefronts per task
+constexpr int kTaskWaves = kTaskBlock / 64;
+
+// Workgroup-shared scratch of one task.
+struct TaskShared {
+    uint32_t cnt[2];
+    uint32_t next_item;
+    uint32_t cand;
+    uint32_t act;
+    uint32_t base;
+    uint32_t task;
+    unsigned long long total;
+    uint32_t trial[64];
+    ArcStage stage[kTaskWaves][64];
+};
+
+// Where one task keeps its state.
+struct TaskCtx {
+    uint32_t w;
+    uint64_t* Aw;          // active masks of the task's word
+    uint64_t* Nw;          // IC: next-step masks (zero between steps)
+    uint32_t* L[2];        // frontier node lists
+    uint64_t* M[2];        // IC: frontier masks
+    uint32_t* C;           // LT: candidates
+    uint32_t* stamp;       // LT: last stamp that collected each node
+    uint32_t stamp_base;   // LT: stamps of this task are stamp_base + step
+    uint32_t* act;         // slot forms: activated nodes (else null)
     const uint32_t* seeds;
     uint32_t n_seeds;
 };
 
-template <bool kSets>
-__device__ __forceinline__ TaskView task_view(const SimParams& P, uint32_t t)
+// IC cascade of one task.  Per step every wavefront takes frontier entries
+// and walks their out-arcs lane-strided; a node's first new bit of the step
+// appends it to the next list (counter in LDS); after a barrier the next
+// list picks up its masks from Nw and clears them.  Returns the step count.
+__device__ __forceinline__ uint32_t ic_task(const SimParams& P, const TaskCtx& c, TaskShared& sh, bool& guard)
 {
-    TaskView v;
-    if (kSets) {
-        v.set = t / P.W;
-        v.w = t % P.W;
-        v.slot = blockIdx.x;
-        const uint32_t b = P.set_off[v.set];
-        v.seeds = P.set_nodes + b;
-        v.n_seeds = P.set_off[v.set + 1] - b;
-    } else {
-        v.set = 0;
-        v.w = t;
-        v.slot = t;
-        v.seeds = P.seeds;
-        v.n_seeds = P.n_seeds;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t w = c.w;
+    const uint64_t vm = valid_mask(w, P.W, P.T);
+    if (threadIdx.x == 0) {
+        sh.cnt[0] = 0;
+        sh.cnt[1] = 0;
+        sh.act = 0;
     }
-    return v;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < c.n_seeds; i += kTaskBlock) {
+        const uint32_t sd = c.seeds[i];
+        c.Aw[sd] = vm;
+        if (c.act) c.act[atomicAdd(&sh.act, 1u)] = sd;
+        if (P.off[sd + 1] > P.off[sd]) {
+            const uint32_t pos = atomicAdd(&sh.cnt[0], 1u);
+            c.L[0][pos] = sd;
+            c.M[0][pos] = vm;
+        }
+    }
+    __syncthreads();
+    uint32_t cur = 0, steps = 0;
+    for (;;) {
+        const uint32_t cnt = sh.cnt[cur];
+        if (cnt == 0) break;
+        if (steps + 1 >= P.cap) {
+            guard = true;
+            break;
+        }
+        ++steps;
+        const uint32_t nxt = cur ^ 1u;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            sh.cnt[nxt] = 0;
+            sh.next_item = 0;
+        }
+        __syncthreads();
+        for (;;) {
+            uint32_t it = 0;
+            if (lane == 0) it = atomicAdd(&sh.next_item, 1u);
+            it = __shfl(it, 0);
+            if (it >= cnt) break;
+            const uint32_t u = (cur ? c.L[1] : c.L[0])[it];
+            const uint64_t mask = (cur ? c.M[1] : c.M[0])[it];
+            const int64_t e1 = P.off[u + 1];
+            for (int64_t e = P.off[u] + lane; e < e1; e += 64) {
+                const uint32_t v = P.idx[e];
+                const uint32_t th = P.thr[e];
+                if (th == 0) continue;
+                const uint64_t todo = mask & ~c.Aw[v];
+                if (todo == 0) continue;
+                const uint64_t live = ic_live(todo, th, (uint64_t)e, w, P.seed);
+                if (live == 0) continue;
+                const uint64_t old = atomic_or64(&c.Aw[v], live);
+                const uint64_t fresh = live & ~old;
+                if (c.act && old == 0) c.act[atomicAdd(&sh.act, 1u)] = v;
+                if (fresh == 0 || P.off[v + 1] == P.off[v]) continue;
+                if (atomic_or64(&c.Nw[v], fresh) == 0) {
+                    const uint32_t pos = atomicAdd(&sh.cnt[nxt], 1u);
+                    (nxt ? c.L[1] : c.L[0])[pos] = v;
+                }
+            }
+        }
+        __syncthreads();
+        const uint32_t nc = sh.cnt[nxt];
+        for (uint32_t i = threadIdx.x; i < nc; i += kTaskBlock) {
+            const uint32_t v = (nxt ? c.L[1] : c.L[0])[i];
+            (nxt ? c.M[1] : c.M[0])[i] = load_relaxed(&c.Nw[v]);
+            c.Nw[v] = 0;
+        }
+        __syncthreads();
+        cur = nxt;
+    }
+    __syncthreads();
+    return steps;
 }
 
-// Sets mode, after a task: add the task's active (node, trial) pairs to
-// totals[set] (and per-node counts when requested) and clear its state rows.
-__device__ __forceinline__ void finish_set_task(const SimParams& P, const TaskView& tv, uint64_t* Aw, const uint32_t* act,
-                                                uint32_t n_act, unsigned long long* s_total)
+// LT cascade of one task.  The frontier list holds the nodes that joined in
+// the previous step (any trial); their out-neighbours with an inactive trial
+// are collected once each into a candidate list (stamp_base + step marks the
+// collection), then wavefronts evaluate candidates eight at a time; nodes
+// that joined form the next frontier.  Returns the step count.
+__device__ __forceinline__ uint32_t lt_task(const SimParams& P, const TaskCtx& c, TaskShared& sh, bool& guard)
 {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t w = c.w;
+    const uint64_t vm = valid_mask(w, P.W, P.T);
+    if (threadIdx.x == 0) {
+        sh.cnt[0] = 0;
+        sh.cnt[1] = 0;
+        sh.act = 0;
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < c.n_seeds; i += kTaskBlock) {
+        const uint32_t sd = c.seeds[i];
+        c.Aw[sd] = vm;
+        c.L[0][atomicAdd(&sh.cnt[0], 1u)] = sd;
+        if (c.act) c.act[atomicAdd(&sh.act, 1u)] = sd;
+    }
+    __syncthreads();
+    uint32_t cur = 0, steps = 0;
+    for (;;) {
+        const uint32_t cnt = sh.cnt[cur];
+        if (cnt == 0) break;
+        if (steps + 1 >= P.cap) {
+            guard = true;
+            break;
+        }
+        ++steps;
+        const uint32_t mark = c.stamp_base + steps;
+        const uint32_t nxt = cur ^ 1u;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            sh.cnt[nxt] = 0;
+            sh.cand = 0;
+            sh.next_item = 0;
+        }
+        __syncthreads();
+        // push side: out-neighbours of the frontier with an inactive trial
+        for (;;) {
+            uint32_t it = 0;
+            if (lane == 0) it = atomicAdd(&sh.next_item, 1u);
+            it = __shfl(it, 0);
+            if (it >= cnt) break;
+            const uint32_t u = (cur ? c.L[1] : c.L[0])[it];
+            const int64_t e1 = P.off[u + 1];
+            for (int64_t e = P.off[u] + lane; e < e1; e += 64) {
+                const uint32_t v = P.idx[e];
+                if ((vm & ~c.Aw[v]) == 0) continue;
+                if (atomicMax(&c.stamp[v], mark) < mark) c.C[atomicAdd(&sh.cand, 1u)] = v;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) sh.next_item = 0;
+        __syncthreads();
+        // pull side: evaluate candidates eight at a time
+        const uint32_t ncand = sh.cand;
+        for (;;) {
+            uint32_t it = 0;
+            if (lane == 0) it = atomicAdd(&sh.next_item, 8u);
+            it = __shfl(it, 0);
+            if (it >= ncand) break;
+            uint64_t vs[8], joined[8];
+            bool first[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) vs[j] = it + j < ncand ? (uint64_t)c.C[it + j] : ~0ull;
+            lt_eval8(P, c.Aw, w, vs, lane, joined, first, sh.stage[threadIdx.x >> 6]);
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (joined[j] && lane == 0) {
+                    (nxt ? c.L[1] : c.L[0])[atomicAdd(&sh.cnt[nxt], 1u)] = (uint32_t)vs[j];
+                    if (c.act && first[j]) c.act[atomicAdd(&sh.act, 1u)] = (uint32_t)vs[j];
+                }
+        }
+        __syncthreads();
+        cur = nxt;
+    }
+    __syncthreads();
+    return steps;
+}
+
+// Slot forms, after a task: fold the listed nodes' masks into the outputs and
+// clear them.  total += sum of popcounts; node_counts[v] += popcount (when
+// given); trial_counts[64w + b] += number of listed nodes with bit b (when
+// given).
+__device__ __forceinline__ void finish_slot_task(const TaskCtx& c, uint32_t n_act, TaskShared& sh, uint64_t* total, uint32_t* node_counts,
+                                 uint32_t* trial_counts, uint32_t T)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    if (threadIdx.x < 64) sh.trial[threadIdx.x] = 0;
+    if (threadIdx.x == 0) sh.total = 0;
+    __syncthreads();
     unsigned long long mine = 0;
-    for (uint32_t i = threadIdx.x; i < n_act; i += kBlock) {
-        const uint32_t v = act[i];
-        const uint32_t c = (uint32_t)__popcll(Aw[v]);
-        mine += c;
-        if (P.set_node_counts) atomicAdd(&P.set_node_counts[(uint64_t)tv.set * (uint64_t)P.n + v], c);
-        Aw[v] = 0;
+    uint32_t tcount = 0;  // this lane's trial (bit) count over the wavefront's nodes
+    for (uint32_t base = (threadIdx.x & ~63u); base < n_act; base += kTaskBlock) {
+        const uint32_t i = base + lane;
+        const uint32_t v = i < n_act ? c.act[i] : 0u;
+        const uint64_t x = i < n_act ? c.Aw[v] : 0ull;
+        const uint32_t pc = (uint32_t)__popcll(x);
+        mine += pc;
+        if (i < n_act) {
+            if (node_counts) atomicAdd(&node_counts[v], pc);
+            c.Aw[v] = 0;
+        }
+        if (trial_counts) {
+            for (uint32_t b = 0; b < 64; ++b) {
+                const uint64_t bal = __ballot((x >> b) & 1ull);
+                tcount += (lane == b) ? (uint32_t)__popcll(bal) : 0u;
+            }
+        }
     }
     for (int o = 32; o > 0; o >>= 1) mine += __shfl_down(mine, o);
-    if ((threadIdx.x & 63u) == 0 && mine) atomicAdd(s_total, mine);
+    if (lane == 0 && mine) atomicAdd(&sh.total, mine);
+    if (trial_counts && tcount) atomicAdd(&sh.trial[lane], tcount);
     __syncthreads();
-    if (threadIdx.x == 0 && *s_total) atomicAdd((unsigned long long*)&P.totals[tv.set], *s_total);
+    if (threadIdx.x == 0 && sh.total) atomicAdd((unsigned long long*)total, sh.total);
+    if (trial_counts && threadIdx.x < 64) {
+        const uint64_t t = (uint64_t)c.w * 64 + threadIdx.x;
+        if (sh.trial[threadIdx.x] && t < T) atomicAdd(&trial_counts[t], sh.trial[threadIdx.x]);
+    }
+    __syncthreads();
 }
 
-// Word-local IC.  Per task: a frontier list of nodes with their masks (node
-// ids in Q[0]/Q[1], masks in Q[2]) and a scratch mask row N[0] that is zero
-// between steps.  Step: every wavefront takes frontier entries and walks their
-// out-arcs lane-strided; a node's first new bit of the step appends it to the
-// next list (counter in LDS); after a barrier the next list picks up its masks
-// from N[0] and clears them.
-template <bool kSets>
-__global__ __launch_bounds__(kBlock) void word_ic_kernel(SimParams P, uint64_t list_cap)
+// Single-set and many-sets forms.
+template <bool kSets, bool kLT>
+__global__ __launch_bounds__(kTaskBlock) void word_kernel(SimParams P, uint64_t list_cap)
 {
-    __shared__ uint32_t s_task;
-    __shared__ uint32_t s_cnt[2];
-    __shared__ uint32_t s_next_item;
-    __shared__ uint32_t s_act;
-    __shared__ unsigned long long s_total;
-    const uint32_t lane = threadIdx.x & 63u;
+    __shared__ TaskShared sh;
     const uint64_t n = (uint64_t)P.n;
     const uint32_t n_tasks = kSets ? P.n_sets * P.W : P.W;
     uint32_t max_steps = 0;
     bool guard = false;
     for (;;) {
         __syncthreads();
-        if (threadIdx.x == 0) s_task = atomicAdd(P.task_counter, 1u);
+        if (threadIdx.x == 0) sh.task = atomicAdd(P.task_counter, 1u);
         __syncthreads();
-        const uint32_t t = s_task;
+        const uint32_t t = sh.task;
         if (t >= n_tasks) break;
-        const TaskView tv = task_view<kSets>(P, t);
-        const uint32_t w = tv.w;
-        const uint64_t vm = valid_mask(w, P.W, P.T);
-        uint64_t* Aw = P.A + tv.slot * n;
-        uint64_t* Nw = P.N[0] + tv.slot * n;
-        uint32_t* L[2] = {(uint32_t*)P.Q[0] + tv.slot * list_cap, (uint32_t*)P.Q[1] + tv.slot * list_cap};
-        uint64_t* M[2] = {(uint64_t*)P.Q[2] + tv.slot * list_cap * 2, (uint64_t*)P.Q[2] + tv.slot * list_cap * 2 + list_cap};
-        uint32_t* act = kSets ? P.act + tv.slot * n : nullptr;
-        if (threadIdx.x == 0) {
-            s_cnt[0] = 0;
-            s_cnt[1] = 0;
-            s_act = 0;
-            s_total = 0;
-        }
-        __syncthreads();
-        for (uint32_t i = threadIdx.x; i < tv.n_seeds; i += kBlock) {
-            const uint32_t sd = tv.seeds[i];
-            Aw[sd] = vm;
-            if (kSets) act[atomicAdd(&s_act, 1u)] = sd;
-            if (P.off[sd + 1] > P.off[sd]) {
-                const uint32_t pos = atomicAdd(&s_cnt[0], 1u);
-                L[0][pos] = sd;
-                M[0][pos] = vm;
-            }
-        }
-        __syncthreads();
-        uint32_t cur = 0, steps = 0;
-        for (;;) {
-            const uint32_t cnt = s_cnt[cur];
-            if (cnt == 0) break;
-            if (steps + 1 >= P.cap) {
-                guard = true;
-                break;
-            }
-            ++steps;
-            const uint32_t nxt = cur ^ 1u;
-            if (threadIdx.x == 0) {
-                s_cnt[nxt] = 0;
-                s_next_item = 0;
-            }
-            __syncthreads();
-            // wavefronts take frontier entries dynamically
-            for (;;) {
-                uint32_t it = 0;
-                if (lane == 0) it = atomicAdd(&s_next_item, 1u);
-                it = __shfl(it, 0);
-                if (it >= cnt) break;
-                const uint32_t u = L[cur][it];
-                const uint64_t mask = M[cur][it];
-                const int64_t e1 = P.off[u + 1];
-                for (int64_t e = P.off[u] + lane; e < e1; e += 64) {
-                    const uint32_t v = P.idx[e];
-                    const uint32_t th = P.thr[e];
-                    if (th == 0) continue;
-                    const uint64_t todo = mask & ~Aw[v];
-                    if (todo == 0) continue;
-                    const uint64_t live = ic_live(todo, th, (uint64_t)e, w, P.seed);
-                    if (live == 0) continue;
-                    const uint64_t old = atomic_or64(&Aw[v], live);
-                    const uint64_t fresh = live & ~old;
-                    if (kSets && old == 0) act[atomicAdd(&s_act, 1u)] = v;
-                    if (fresh == 0 || P.off[v + 1] == P.off[v]) continue;
-                    if (atomic_or64(&Nw[v], fresh) == 0) {
-                        const uint32_t pos = atomicAdd(&s_cnt[nxt], 1u);
-                        L[nxt][pos] = v;
-                    }
-                }
-            }
-            __syncthreads();
-            const uint32_t nc = s_cnt[nxt];
-            for (uint32_t i = threadIdx.x; i < nc; i += kBlock) {
-                const uint32_t v = L[nxt][i];
-                M[nxt][i] = load_relaxed(&Nw[v]);
-                Nw[v] = 0;
-            }
-            __syncthreads();
-            cur = nxt;
-        }
-        if (kSets) finish_set_task(P, tv, Aw, act, s_act, &s_total);
-        max_steps = steps > max_steps ? steps : max_steps;
-    }
-    if (threadIdx.x == 0) {
-        atomicMax(&P.status[0], max_steps);
-        if (guard) P.status[1] = 1;
-    }
-}
-
-// Word-local LT.  Per task: the frontier list holds the nodes that joined in
-// the previous step (any trial); their out-neighbours with an inactive trial
-// are collected once each into a candidate list (a per-node stamp records the
-// last step that collected it), then wavefronts evaluate candidates eight at
-// a time; nodes that joined form the next frontier.  Single-set mode clears
-// its stamps at the end of the word; sets mode numbers steps with a per-slot
-// counter that only grows, so old stamps never match.
-template <bool kSets>
-__global__ __launch_bounds__(kBlock) void word_lt_kernel(SimParams P, uint64_t list_cap)
-{
-    __shared__ ArcStage stage[kWaves][64];
-    __shared__ uint32_t s_task;
-    __shared__ uint32_t s_cnt[2];
-    __shared__ uint32_t s_cand;
-    __shared__ uint32_t s_next_item;
-    __shared__ uint32_t s_act;
-    __shared__ uint32_t s_base;
-    __shared__ unsigned long long s_total;
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint64_t n = (uint64_t)P.n;
-    const uint32_t n_tasks = kSets ? P.n_sets * P.W : P.W;
-    uint32_t max_steps = 0;
-    bool guard = false;
-    for (;;) {
-        __syncthreads();
-        if (threadIdx.x == 0) s_task = atomicAdd(P.task_counter, 1u);
-        __syncthreads();
-        const uint32_t t = s_task;
-        if (t >= n_tasks) break;
-        const TaskView tv = task_view<kSets>(P, t);
-        const uint32_t w = tv.w;
-        const uint64_t vm = valid_mask(w, P.W, P.T);
-        uint64_t* Aw = P.A + tv.slot * n;
-        uint32_t* stamp = (kSets ? P.sstamp : P.aux) + tv.slot * n;
-        uint32_t* F[2] = {(uint32_t*)P.Q[0] + tv.slot * list_cap, (uint32_t*)P.Q[1] + tv.slot * list_cap};
-        uint32_t* C = (uint32_t*)P.Q[2] + tv.slot * list_cap;
-        uint32_t* act = kSets ? P.act + tv.slot * n : nullptr;
-        if (threadIdx.x == 0) {
-            s_cnt[0] = 0;
-            s_cnt[1] = 0;
-            s_act = 0;
-            s_total = 0;
-            s_base = kSets ? P.slot_steps[tv.slot] : 0u;
-        }
-        __syncthreads();
-        const uint32_t base = s_base;
-        for (uint32_t i = threadIdx.x; i < tv.n_seeds; i += kBlock) {
-            const uint32_t sd = tv.seeds[i];
-            Aw[sd] = vm;
-            const uint32_t pos = atomicAdd(&s_cnt[0], 1u);
-            F[0][pos] = sd;
-            if (kSets) act[atomicAdd(&s_act, 1u)] = sd;
-        }
-        __syncthreads();
-        uint32_t cur = 0, steps = 0;
-        for (;;) {
-            const uint32_t cnt = s_cnt[cur];
-            if (cnt == 0) break;
-            if (steps + 1 >= P.cap) {
-                guard = true;
-                break;
-            }
-            ++steps;
-            const uint32_t mark = base + steps;
-            const uint32_t nxt = cur ^ 1u;
-            if (threadIdx.x == 0) {
-                s_cnt[nxt] = 0;
-                s_cand = 0;
-                s_next_item = 0;
-            }
-            __syncthreads();
-            // push side: out-neighbours of the frontier with an inactive trial
-            for (;;) {
-                uint32_t it = 0;
-                if (lane == 0) it = atomicAdd(&s_next_item, 1u);
-                it = __shfl(it, 0);
-                if (it >= cnt) break;
-                const uint32_t u = F[cur][it];
-                const int64_t e1 = P.off[u + 1];
-                for (int64_t e = P.off[u] + lane; e < e1; e += 64) {
-                    const uint32_t v = P.idx[e];
-                    if ((vm & ~Aw[v]) == 0) continue;
-                    if (atomicMax(&stamp[v], mark) < mark) {
-                        const uint32_t pos = atomicAdd(&s_cand, 1u);
-                        C[pos] = v;
-                    }
-                }
-            }
-            __syncthreads();
-            if (threadIdx.x == 0) s_next_item = 0;
-            __syncthreads();
-            // pull side: evaluate candidates eight at a time
-            const uint32_t ncand = s_cand;
-            for (;;) {
-                uint32_t it = 0;
-                if (lane == 0) it = atomicAdd(&s_next_item, 8u);
-                it = __shfl(it, 0);
-                if (it >= ncand) break;
-                uint64_t vs[8], joined[8];
-                bool first[8];
-#pragma unroll
-                for (int j = 0; j < 8; ++j) vs[j] = it + j < ncand ? (uint64_t)C[it + j] : ~0ull;
-                lt_eval8(P, Aw, w, vs, lane, joined, first, stage[threadIdx.x >> 6]);
-#pragma unroll
-                for (int j = 0; j < 8; ++j)
-                    if (joined[j] && lane == 0) {
-                        const uint32_t pos = atomicAdd(&s_cnt[nxt], 1u);
-                        F[nxt][pos] = (uint32_t)vs[j];
-                        if (kSets && first[j]) act[atomicAdd(&s_act, 1u)] = (uint32_t)vs[j];
-                    }
-            }
-            __syncthreads();
-            cur = nxt;
-        }
-        __syncthreads();
+        TaskCtx c;
+        uint32_t set = 0;
+        uint64_t slot;
         if (kSets) {
-            if (threadIdx.x == 0) P.slot_steps[tv.slot] = base + steps + 1;
-            finish_set_task(P, tv, Aw, act, s_act, &s_total);
+            set = t / P.W;
+            c.w = t % P.W;
+            slot = blockIdx.x;
+            const uint32_t b = P.set_off[set];
+            c.seeds = P.set_nodes + b;
+            c.n_seeds = P.set_off[set + 1] - b;
+            c.act = P.act + slot * n;
         } else {
-            // clear this word's stamps for the next run
-            for (uint64_t v = threadIdx.x; v < n; v += kBlock) stamp[v] = 0;
+            c.w = t;
+            slot = t;
+            c.seeds = P.seeds;
+            c.n_seeds = P.n_seeds;
+            c.act = nullptr;
         }
+        c.Aw = P.A + slot * n;
+        c.L[0] = (uint32_t*)P.Q[0] + slot * list_cap;
+        c.L[1] = (uint32_t*)P.Q[1] + slot * list_cap;
+        if (!kLT) {
+            c.Nw = P.N[0] + slot * n;
+            c.M[0] = (uint64_t*)P.Q[2] + slot * list_cap * 2;
+            c.M[1] = c.M[0] + list_cap;
+            c.C = nullptr;
+            c.stamp = nullptr;
+            c.stamp_base = 0;
+        } else {
+            c.Nw = nullptr;
+            c.M[0] = c.M[1] = nullptr;
+            c.C = (uint32_t*)P.Q[2] + slot * list_cap;
+            c.stamp = (kSets ? P.sstamp : P.aux) + slot * n;
+            if (threadIdx.x == 0) sh.base = kSets ? P.slot_steps[slot] : 0u;
+            __syncthreads();
+            c.stamp_base = sh.base;
+        }
+        const uint32_t steps = kLT ? lt_task(P, c, sh, guard) : ic_task(P, c, sh, guard);
+        if (kLT) {
+            if (kSets) {
+                if (threadIdx.x == 0) P.slot_steps[slot] = c.stamp_base + steps + 1;
+            } else {
+                for (uint64_t v = threadIdx.x; v < n; v += kTaskBlock) c.stamp[v] = 0;
+            }
+        }
+        if (kSets) finish_slot_task(c, sh.act, sh, &P.totals[set], P.set_node_counts ? P.set_node_counts + (uint64_t)set * n : nullptr,
+                                    nullptr, P.T);
         max_steps = steps > max_steps ? steps : max_steps;
     }
     if (threadIdx.x == 0) {
         atomicMax(&P.status[0], max_steps);
         if (guard) P.status[1] = 1;
+    }
+}
+
+// One item of a batch: its graph and run parameters (P.seeds, P.n_seeds,
+// P.T, P.W, P.seed) and its outputs.
+struct BatchItem {
+    SimParams P;
+    int model;
+    uint32_t* trial_counts;  // [T]
+    uint32_t* node_counts;   // [n] or null
+    uint64_t* total;         // [1]
+};
+
+// Batch form: tasks[t] = item << 12 | word, in the order the schedule chose.
+// Slot state rows are sized for the largest item.
+__global__ __launch_bounds__(kTaskBlock) void batch_kernel(const BatchItem* __restrict__ items, const uint32_t* __restrict__ tasks,
+                                                       uint32_t n_tasks, uint32_t* task_counter, uint64_t max_n,
+                                                       uint64_t* sA, uint64_t* sN, uint32_t* sQ0, uint32_t* sQ1, uint64_t* sQ2,
+                                                       uint32_t* sact, uint32_t* sstamp, uint32_t* slot_steps, uint32_t* status)
+{
+    __shared__ TaskShared sh;
+    const uint64_t slot = blockIdx.x;
+    uint32_t max_steps = 0;
+    bool guard = false;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) sh.task = atomicAdd(task_counter, 1u);
+        __syncthreads();
+        const uint32_t t = sh.task;
+        if (t >= n_tasks) break;
+        const uint32_t code = tasks[t];
+        const BatchItem& it = items[code >> 12];
+        const SimParams& P = it.P;
+        TaskCtx c;
+        c.w = code & 0xFFFu;
+        c.seeds = P.seeds;
+        c.n_seeds = P.n_seeds;
+        c.act = sact + slot * max_n;
+        c.Aw = sA + slot * max_n;
+        c.L[0] = sQ0 + slot * max_n;
+        c.L[1] = sQ1 + slot * max_n;
+        c.Nw = sN + slot * max_n;
+        c.M[0] = sQ2 + slot * max_n * 2;
+        c.M[1] = c.M[0] + max_n;
+        c.C = (uint32_t*)(sQ2 + slot * max_n * 2);
+        c.stamp = sstamp + slot * max_n;
+        if (threadIdx.x == 0) sh.base = slot_steps[slot];
+        __syncthreads();
+        c.stamp_base = sh.base;
+        const bool lt = it.model != 0;
+        const uint32_t steps = lt ? lt_task(P, c, sh, guard) : ic_task(P, c, sh, guard);
+        if (threadIdx.x == 0 && lt) slot_steps[slot] = c.stamp_base + steps + 1;
+        finish_slot_task(c, sh.act, sh, it.total, it.node_counts, it.trial_counts, P.T);
+        max_steps = steps > max_steps ? steps : max_steps;
+    }
+    if (threadIdx.x == 0) {
+        atomicMax(&status[0], max_steps);
+        if (guard) status[1] = 1;
     }
 }
 

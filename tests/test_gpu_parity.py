@@ -239,3 +239,50 @@ def test_celf_equals_greedy_and_oracle_greedy(ims):
     assert S == a["seeds"]
     assert a["evaluations"] < b["evaluations"]
     G.close()
+
+
+def _batch_items(ims, count=10, seed=3):
+    rng = np.random.default_rng(seed)
+    items, specs = [], []
+    for i in range(count):
+        n = int(rng.integers(300, 4000))
+        g = synth.erdos_renyi_directed(n, 6.0, 50 + i) if i % 2 == 0 else synth.barabasi_albert(n, 3, 50 + i)
+        model = "ic" if (i // 2) % 2 == 0 else "lt"
+        param = synth.weighted_cascade(g)
+        seeds = synth.random_seeds(n, int(rng.integers(0, 12)), 70 + i)
+        T = int(rng.choice([1, 64, 100, 190]))
+        G = ims.Graph(g.n, g.offsets, g.indices, model, param)
+        items.append((G, seeds, T, 900 + i))
+        specs.append((model, g, param, seeds, T, 900 + i))
+    return items, specs
+
+
+def test_batch_equals_single_runs_across_graph_replays(ims):
+    """One persistent launch over uneven graphs, IC and LT mixed; the captured
+    HIP graph is replayed several times with eager work in between, and every
+    replay equals the per-item runs (and the oracle totals)."""
+    import torch
+    items, specs = _batch_items(ims)
+    singles = [ims.simulate(G, sd, T, rs) for (G, sd, T, rs) in items]
+    B = ims.Batch(items)
+    for rep in range(3):
+        say(f"[parity] batch replay {rep}")
+        B.launch()
+        torch.cuda.synchronize()
+        x = torch.randn(1000, device="cuda").sum()  # eager work between replays
+        res = B.results()
+        for k, (r, s1) in enumerate(zip(res, singles)):
+            assert r["total"] == s1["total"], (rep, k)
+            assert (r["trial_counts"] == s1["trial_counts"].cpu().numpy().view(np.uint32)).all(), (rep, k)
+            assert (r["node_counts"] == s1["node_counts"].cpu().numpy().view(np.uint32)).all(), (rep, k)
+    for (model, g, param, sd, T, rs), r in zip(specs, res):
+        ref = oracle.simulate(model, g.n, g.offsets, g.indices, oracle.encode(model, param), sd, T, rs, want_bits=False)
+        assert r["total"] == ref["total"]
+    chosen = B.autotune(repeats=1)
+    assert chosen[0] >= 1
+    B.launch()
+    torch.cuda.synchronize()
+    assert [r["total"] for r in B.results()] == [s1["total"] for s1 in singles]
+    B.close()
+    for it in items:
+        it[0].close()
