@@ -60,7 +60,7 @@ def load_alg_bytes(workload: str, graph_sha: str, n_trials: int, rng_seed: int):
 def load_traffic(workload: str):
     """Measured HBM bytes per launch from committed rocprofv3 counter runs,
     valid only while the kernel sources are unchanged."""
-    path = os.path.join(ROOT, "profiles", f"traffic_sim_persistent_{workload}.json")
+    path = os.path.join(ROOT, "profiles", f"traffic_simulate_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -171,7 +171,7 @@ def main() -> int:
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": None if traffic is None else traffic["bytes_per_launch"],
-                    "kernel": "sim_persistent", "kernel_ms": round(kernel_avg_s * 1e3, 4),
+                    "kernel": "ims_simulate call (ltg_sweep_kernel sweeps, threshold table, reductions)", "kernel_ms": round(kernel_avg_s * 1e3, 4),
                     "alg_bytes_per_launch": alg["bytes"], "alg_units_per_launch": alg["units"]}
 
     cpu = None
