@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libimsim.so")
-SOURCES = [os.path.join(HERE, "csrc", "imsim.hip")]
+SOURCES = [os.path.join(HERE, "csrc", "imsim.hip"), os.path.join(HERE, "csrc", "mpnn.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -75,6 +75,16 @@ int fill_async(Tv* p, uint64_t count, Tv value, hipStream_t s)
 
 }  // namespace
 
+namespace imsim {
+// lets the other translation units of the library set the calling thread's
+// ims_last_error() message
+int record_error(int code, const char* msg)
+{
+    g_last_error = msg;
+    return code;
+}
+}  // namespace imsim
+
 struct ims_graph {
     int device = 0;
     int64_t n = 0, m = 0;

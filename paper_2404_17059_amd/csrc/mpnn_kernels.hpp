@@ -1,0 +1,512 @@
+// HIP kernels of the learned spread estimator (a message-passing network over
+// the diffusion graph) for gfx950.
+//
+// Tensors of a batch of B seed sets on one graph are node-major: row r = v*B + b
+// holds the features of node v for set b, so an aggregation over the arcs into
+// v reads, per arc, one contiguous run of B*D values of the source node.
+// Activations and gradients are stored in bf16 (raw uint16 bits); every sum is
+// accumulated in fp32.  Dense layers run on the bf16 matrix cores
+// (v_mfma_f32_16x16x32_bf16); the data-row axis is the MFMA column axis so a
+// lane's four outputs are four consecutive channels of one row (8-byte stores).
+// Reductions over rows write per-workgroup partials that a second kernel sums
+// in a fixed order, so every result is deterministic.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace imsim_mpnn {
+
+constexpr int kHidden = 64;    // channels of every hidden layer
+constexpr int kIn = 16;        // padded width of the input features (4 used)
+constexpr int kThreads = 256;  // threads of every workgroup here
+constexpr int kWStage = 128;   // rows per LDS stage of the weight-gradient kernel
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// bf16 <-> fp32.  Rounding is to nearest, ties to even; NaN stays NaN.
+__device__ __forceinline__ float bf2f(uint32_t h) { return __uint_as_float(h << 16); }
+
+__device__ __forceinline__ uint32_t f2bf(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+
+__device__ __forceinline__ uint32_t pack2(float lo, float hi) { return f2bf(lo) | (f2bf(hi) << 16); }
+
+// eight bf16 held as four 32-bit words -> eight floats
+__device__ __forceinline__ void unpack8(const u32x4& r, float* f)
+{
+    #pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        f[2 * i] = __uint_as_float(r[i] << 16);
+        f[2 * i + 1] = __uint_as_float(r[i] & 0xffff0000u);
+    }
+}
+
+__device__ __forceinline__ floatx4 mfma(const u32x4& a, const u32x4& b, floatx4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0, 0,
+                                                   0);
+}
+
+// ---------------------------------------------------------------------------
+// Input features.  Row r = v*B + b gets [s, f1(v), f2(v), f3(v), 0 ...] with
+// s = 0; a second kernel sets s = 1 for the members of each set.
+
+__global__ void features_kernel(int64_t rows, uint32_t B, const float* __restrict__ node_feat, uint16_t* __restrict__ X)
+{
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < rows; r += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = r / B;
+        u32x4 lo, hi = {0u, 0u, 0u, 0u};
+        lo[0] = pack2(0.0f, node_feat[v * 3 + 0]);
+        lo[1] = pack2(node_feat[v * 3 + 1], node_feat[v * 3 + 2]);
+        lo[2] = 0u;
+        lo[3] = 0u;
+        u32x4* dst = (u32x4*)(X + r * kIn);
+        dst[0] = lo;
+        dst[1] = hi;
+    }
+}
+
+__global__ void seed_scatter_kernel(uint32_t n_sets, uint32_t B, const uint32_t* __restrict__ set_off,
+                                    const uint32_t* __restrict__ set_nodes, uint16_t* __restrict__ X)
+{
+    const uint32_t total = set_off[n_sets];
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < total; k += gridDim.x * blockDim.x) {
+        // set b owns positions [set_off[b], set_off[b+1]): binary search
+        uint32_t lo = 0, hi = n_sets;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) / 2;
+            if (set_off[mid] <= k) lo = mid; else hi = mid;
+        }
+        const uint64_t r = (uint64_t)set_nodes[k] * B + lo;
+        X[r * kIn] = 0x3f80;  // 1.0
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Sparse aggregation.  Y[v] = sum over arcs e of the CSR row of v of
+// w[e] * X[nbr[e]], where a node row holds C = B*D bf16 values.  A lane owns
+// eight consecutive values (16 bytes); nodes with C/8 < 256 chunks share a
+// workgroup.  Forward: CSR = arcs into v, Y = M.  Backward: CSR = arcs out of
+// v, and the epilogue adds `add` and zeroes where `relu_of` <= 0 (the ReLU of
+// the layer below), producing that layer's pre-activation gradient.
+
+template <bool kBackward>
+__global__ void __launch_bounds__(kThreads) spmm_kernel(int64_t n, uint32_t C, const int64_t* __restrict__ off,
+                                                        const uint32_t* __restrict__ nbr, const float* __restrict__ w,
+                                                        const uint16_t* __restrict__ X, uint16_t* __restrict__ Y,
+                                                        const uint16_t* __restrict__ add,
+                                                        const uint16_t* __restrict__ relu_of)
+{
+    const uint32_t nc = C / 8;
+    const uint32_t per_block = nc >= kThreads ? 1u : kThreads / nc;
+    const uint32_t local = nc >= kThreads ? 0u : threadIdx.x / nc;
+    const int64_t v = (int64_t)blockIdx.x * per_block + local;
+    if (local >= per_block || v >= n) return;
+    const int64_t e0 = off[v], e1 = off[v + 1];
+    const uint32_t step = nc >= kThreads ? kThreads : nc;
+    for (uint32_t j = nc >= kThreads ? threadIdx.x : threadIdx.x % nc; j < nc; j += step) {
+        float acc[8];
+        #pragma unroll
+        for (int i = 0; i < 8; ++i) acc[i] = 0.0f;
+        int64_t e = e0;
+        for (; e + 4 <= e1; e += 4) {
+            u32x4 r[4];
+            float a[4];
+            #pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t u = nbr[e + q];
+                a[q] = w[e + q];
+                r[q] = *(const u32x4*)(X + (uint64_t)u * C + (uint64_t)j * 8);
+            }
+            #pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                float f[8];
+                unpack8(r[q], f);
+                #pragma unroll
+                for (int i = 0; i < 8; ++i) acc[i] = fmaf(a[q], f[i], acc[i]);
+            }
+        }
+        for (; e < e1; ++e) {
+            const uint32_t u = nbr[e];
+            const float a = w[e];
+            const u32x4 r = *(const u32x4*)(X + (uint64_t)u * C + (uint64_t)j * 8);
+            float f[8];
+            unpack8(r, f);
+            #pragma unroll
+            for (int i = 0; i < 8; ++i) acc[i] = fmaf(a, f[i], acc[i]);
+        }
+        const uint64_t o = (uint64_t)v * C + (uint64_t)j * 8;
+        if constexpr (kBackward) {
+            float d[8], h[8];
+            unpack8(*(const u32x4*)(add + o), d);
+            unpack8(*(const u32x4*)(relu_of + o), h);
+            #pragma unroll
+            for (int i = 0; i < 8; ++i) acc[i] = h[i] > 0.0f ? acc[i] + d[i] : 0.0f;
+        }
+        u32x4 out;
+        #pragma unroll
+        for (int i = 0; i < 4; ++i) out[i] = pack2(acc[2 * i], acc[2 * i + 1]);
+        *(u32x4*)(Y + o) = out;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Dense layer, forward.  Y = ReLU([Xs | Xn] W + b) for rows [0, R):
+// Xs, Xn are [R][D] bf16, W is [2D][64] fp32 (rounded to bf16 here), b [64],
+// Y [R][64] bf16.  MFMA: A = W^T tile (channel x k), B = X^T tile (k x row).
+
+template <int D>
+__global__ void __launch_bounds__(kThreads) dense_fwd_kernel(int64_t R, const uint16_t* __restrict__ Xs,
+                                                             const uint16_t* __restrict__ Xn,
+                                                             const float* __restrict__ W, const float* __restrict__ bias,
+                                                             uint16_t* __restrict__ Y)
+{
+    constexpr int K = 2 * D;
+    constexpr int KS = K / 32;      // MFMA k-steps
+    constexpr int P = K + 8;        // LDS pitch (bf16) of W^T rows
+    __shared__ uint16_t Wt[kHidden * P];
+    for (int i = threadIdx.x; i < K * kHidden; i += kThreads) {
+        const int k = i / kHidden, c = i % kHidden;
+        Wt[c * P + k] = (uint16_t)f2bf(W[i]);
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int l16 = lane & 15, g = lane >> 4;
+    u32x4 A[4][KS];
+    #pragma unroll
+    for (int ct = 0; ct < 4; ++ct)
+        #pragma unroll
+        for (int ks = 0; ks < KS; ++ks) A[ct][ks] = *(const u32x4*)(Wt + (16 * ct + l16) * P + 32 * ks + 8 * g);
+    float bv[4][4];
+    #pragma unroll
+    for (int ct = 0; ct < 4; ++ct)
+        #pragma unroll
+        for (int q = 0; q < 4; ++q) bv[ct][q] = bias[16 * ct + 4 * g + q];
+
+    const int64_t tiles = (R + 15) / 16;
+    const int64_t wave = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+    const int64_t waves = (int64_t)gridDim.x * (kThreads / 64);
+    for (int64_t t = wave; t < tiles; t += waves) {
+        const int64_t row = t * 16 + l16;
+        const bool ok = row < R;
+        u32x4 Bf[KS];
+        #pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const int kc = 32 * ks + 8 * g;
+            const uint16_t* src = kc < D ? Xs + row * D + kc : Xn + row * D + (kc - D);
+            Bf[ks] = ok ? *(const u32x4*)src : u32x4{0u, 0u, 0u, 0u};
+        }
+        floatx4 acc[4];
+        #pragma unroll
+        for (int ct = 0; ct < 4; ++ct) {
+            acc[ct] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+            #pragma unroll
+            for (int ks = 0; ks < KS; ++ks) acc[ct] = mfma(A[ct][ks], Bf[ks], acc[ct]);
+        }
+        if (ok) {
+            #pragma unroll
+            for (int ct = 0; ct < 4; ++ct) {
+                float y[4];
+                #pragma unroll
+                for (int q = 0; q < 4; ++q) y[q] = fmaxf(acc[ct][q] + bv[ct][q], 0.0f);
+                u32x2 o = {pack2(y[0], y[1]), pack2(y[2], y[3])};
+                *(u32x2*)(Y + row * kHidden + 16 * ct + 4 * g) = o;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Dense layer, input gradient.  [dXs | dXn] = dZ W^T: dZ [R][64] bf16,
+// W [2D][64] fp32; outputs [R][D] bf16 each.  MFMA: A = W tile (k x channel),
+// B = dZ^T tile (channel x row).
+
+template <int D>
+__global__ void __launch_bounds__(kThreads) dense_bwd_data_kernel(int64_t R, const uint16_t* __restrict__ dZ,
+                                                                  const float* __restrict__ W,
+                                                                  uint16_t* __restrict__ dXs, uint16_t* __restrict__ dXn)
+{
+    constexpr int K = 2 * D;
+    constexpr int KT = K / 16;       // 16-wide tiles of the output columns
+    constexpr int P = kHidden + 8;   // LDS pitch of W rows
+    __shared__ uint16_t Wb[K * P];
+    for (int i = threadIdx.x; i < K * kHidden; i += kThreads) Wb[(i / kHidden) * P + i % kHidden] = (uint16_t)f2bf(W[i]);
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int l16 = lane & 15, g = lane >> 4;
+    u32x4 A[KT][2];
+    #pragma unroll
+    for (int kt = 0; kt < KT; ++kt)
+        #pragma unroll
+        for (int ks = 0; ks < 2; ++ks) A[kt][ks] = *(const u32x4*)(Wb + (16 * kt + l16) * P + 32 * ks + 8 * g);
+
+    const int64_t tiles = (R + 15) / 16;
+    const int64_t wave = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+    const int64_t waves = (int64_t)gridDim.x * (kThreads / 64);
+    for (int64_t t = wave; t < tiles; t += waves) {
+        const int64_t row = t * 16 + l16;
+        const bool ok = row < R;
+        u32x4 Bf[2];
+        #pragma unroll
+        for (int ks = 0; ks < 2; ++ks)
+            Bf[ks] = ok ? *(const u32x4*)(dZ + row * kHidden + 32 * ks + 8 * g) : u32x4{0u, 0u, 0u, 0u};
+        #pragma unroll
+        for (int kt = 0; kt < KT; ++kt) {
+            floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            acc = mfma(A[kt][0], Bf[0], acc);
+            acc = mfma(A[kt][1], Bf[1], acc);
+            if (ok) {
+                const int k = 16 * kt + 4 * g;
+                u32x2 o = {pack2(acc[0], acc[1]), pack2(acc[2], acc[3])};
+                uint16_t* dst = k < D ? dXs + row * D + k : dXn + row * D + (k - D);
+                *(u32x2*)dst = o;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Dense layer, weight and bias gradients.  dW = [Xs | Xn]^T dZ ([2D][64]) and
+// db = column sums of dZ, over rows [0, R).  Workgroup `blk` takes rows
+// [blk*rows_per, (blk+1)*rows_per) (rows_per a multiple of kWStage), stages
+// kWStage rows of dZ and X transposed into LDS, and accumulates dW^T tiles
+// (channel x k) with MFMA over the row axis.  Partials: part[blk * stride]
+// holds dW ([2D][64]) followed by db ([64]).
+
+template <int D>
+__global__ void __launch_bounds__(kThreads) dense_bwd_weight_kernel(int64_t R, int64_t rows_per,
+                                                                    const uint16_t* __restrict__ Xs,
+                                                                    const uint16_t* __restrict__ Xn,
+                                                                    const uint16_t* __restrict__ dZ,
+                                                                    float* __restrict__ part, int64_t stride)
+{
+    constexpr int K = 2 * D;
+    constexpr int P = kWStage + 8;           // LDS pitch (bf16) of transposed rows
+    constexpr int NT = 4 * (K / 16);         // output tiles (channel tile x k tile)
+    constexpr int TPW = NT / 4;              // tiles per wave
+    __shared__ uint16_t dZt[kHidden * P];
+    __shared__ uint16_t Xt[K * P];
+    __shared__ float red[kThreads / 8][kHidden + 1];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
+    const int l16 = lane & 15, g = lane >> 4;
+    const int64_t r_begin = (int64_t)blockIdx.x * rows_per;
+    const int64_t r_end = r_begin + rows_per < R ? r_begin + rows_per : R;
+
+    floatx4 acc[TPW];
+    #pragma unroll
+    for (int i = 0; i < TPW; ++i) acc[i] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    float db[8];
+    #pragma unroll
+    for (int i = 0; i < 8; ++i) db[i] = 0.0f;
+
+    for (int64_t r0 = r_begin; r0 < r_end; r0 += kWStage) {
+        // stage dZ: kWStage rows x 8 chunks of 8 channels
+        #pragma unroll
+        for (int p = 0; p < kWStage * 8 / kThreads; ++p) {
+            const int ci = tid + kThreads * p;
+            const int row = ci >> 3, ch = ci & 7;
+            const int64_t r = r0 + row;
+            u32x4 raw = r < r_end ? *(const u32x4*)(dZ + r * kHidden + 8 * ch) : u32x4{0u, 0u, 0u, 0u};
+            float f[8];
+            unpack8(raw, f);
+            #pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                db[q] += f[q];
+                dZt[(8 * ch + q) * P + row] = (uint16_t)(q & 1 ? raw[q >> 1] >> 16 : raw[q >> 1] & 0xffffu);
+            }
+        }
+        // stage X: kWStage rows x K/8 chunks
+        constexpr int XC = K / 8;
+        for (int ci = tid; ci < kWStage * XC; ci += kThreads) {
+            const int row = ci / XC, ch = ci % XC;
+            const int64_t r = r0 + row;
+            const int k = 8 * ch;
+            const uint16_t* src = k < D ? Xs + r * D + k : Xn + r * D + (k - D);
+            u32x4 raw = r < r_end ? *(const u32x4*)src : u32x4{0u, 0u, 0u, 0u};
+            #pragma unroll
+            for (int q = 0; q < 8; ++q)
+                Xt[(k + q) * P + row] = (uint16_t)(q & 1 ? raw[q >> 1] >> 16 : raw[q >> 1] & 0xffffu);
+        }
+        __syncthreads();
+        #pragma unroll
+        for (int i = 0; i < TPW; ++i) {
+            const int tau = wv * TPW + i;
+            const int ct = tau & 3, kt = tau >> 2;
+            #pragma unroll
+            for (int rs = 0; rs < kWStage / 32; ++rs) {
+                const u32x4 a = *(const u32x4*)(dZt + (16 * ct + l16) * P + 32 * rs + 8 * g);
+                const u32x4 b = *(const u32x4*)(Xt + (16 * kt + l16) * P + 32 * rs + 8 * g);
+                acc[i] = mfma(a, b, acc[i]);
+            }
+        }
+        __syncthreads();
+    }
+    float* pw = part + (int64_t)blockIdx.x * stride;
+    #pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+        const int tau = wv * TPW + i;
+        const int ct = tau & 3, kt = tau >> 2;
+        const int k = 16 * kt + l16;
+        *(floatx4*)(pw + k * kHidden + 16 * ct + 4 * g) = acc[i];
+    }
+    // bias: threads with equal tid % 8 own the same eight channels
+    #pragma unroll
+    for (int q = 0; q < 8; ++q) red[tid >> 3][8 * (tid & 7) + q] = db[q];
+    __syncthreads();
+    if (tid < kHidden) {
+        float s = 0.0f;
+        for (int j = 0; j < kThreads / 8; ++j) s += red[j][tid];
+        pw[K * kHidden + tid] = s;
+    }
+}
+
+// out[i] = sum over blk of part[blk * stride + i], i < count, fixed order
+__global__ void sum_partials_kernel(int64_t count, int64_t blocks, int64_t stride, const float* __restrict__ part,
+                                    float* __restrict__ out)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    float s = 0.0f;
+    for (int64_t b = 0; b < blocks; ++b) s += part[b * stride + i];
+    out[i] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Readout.  z = H3[r] . w_o + b_o (w_o rounded to bf16), yhat = 1 for a seed
+// (input feature s = 1), else sigmoid(z).  Eight lanes per row.
+
+__global__ void __launch_bounds__(kThreads) readout_fwd_kernel(int64_t R, const uint16_t* __restrict__ H,
+                                                               const uint16_t* __restrict__ X0,
+                                                               const float* __restrict__ w_o, float* __restrict__ Yhat)
+{
+    const int sub = threadIdx.x & 7;
+    float wv[8];
+    #pragma unroll
+    for (int i = 0; i < 8; ++i) wv[i] = bf2f(f2bf(w_o[8 * sub + i]));
+    const float b_o = w_o[kHidden];
+    const int64_t groups = (int64_t)gridDim.x * (kThreads / 8);
+    for (int64_t r = blockIdx.x * (int64_t)(kThreads / 8) + (threadIdx.x >> 3); r < R; r += groups) {
+        float h[8];
+        unpack8(*(const u32x4*)(H + r * kHidden + 8 * sub), h);
+        float z = 0.0f;
+        #pragma unroll
+        for (int i = 0; i < 8; ++i) z = fmaf(h[i], wv[i], z);
+        z += __shfl_xor(z, 1);
+        z += __shfl_xor(z, 2);
+        z += __shfl_xor(z, 4);
+        if (sub == 0) {
+            const bool seed = X0[r * kIn] != 0;
+            Yhat[r] = seed ? 1.0f : 1.0f / (1.0f + expf(-(z + b_o)));
+        }
+    }
+}
+
+// part[blk][b] = sum over nodes v of workgroup blk's range of Yhat[v*B + b]
+// (B <= 256).  Threads (b = tid % Bp, j = tid / Bp), Bp = pow2 >= B.
+__global__ void __launch_bounds__(kThreads) column_partials_kernel(int64_t n, uint32_t B, uint32_t Bp, int64_t nodes_per,
+                                                                   const float* __restrict__ Y, float* __restrict__ part)
+{
+    __shared__ float red[kThreads];
+    const uint32_t b = threadIdx.x % Bp, j = threadIdx.x / Bp, J = kThreads / Bp;
+    const int64_t v0 = (int64_t)blockIdx.x * nodes_per;
+    const int64_t v1 = v0 + nodes_per < n ? v0 + nodes_per : n;
+    float s = 0.0f;
+    if (b < B)
+        for (int64_t v = v0 + j; v < v1; v += J) s += Y[v * B + b];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (uint32_t h = J / 2; h > 0; h /= 2) {
+        if (j < h) red[threadIdx.x] += red[threadIdx.x + h * Bp];
+        __syncthreads();
+    }
+    if (j == 0 && b < B) part[(int64_t)blockIdx.x * B + b] = red[threadIdx.x];
+}
+
+// g[b] = d loss / d pred[b] and loss = mean over b of ((pred - target)/n)^2
+__global__ void loss_kernel(uint32_t B, double n, const float* __restrict__ pred, const float* __restrict__ target,
+                            float* __restrict__ g, float* __restrict__ loss)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    float L = 0.0f;
+    const float inv_n = (float)(1.0 / n);
+    for (uint32_t b = 0; b < B; ++b) {
+        const float d = (pred[b] - target[b]) * inv_n;
+        L += d * d;
+        g[b] = 2.0f * d * inv_n / (float)B;
+    }
+    if (loss) loss[0] = L / (float)B;
+}
+
+// Readout backward.  dz = g[b] * yhat (1 - yhat) (zero for seeds, whose yhat
+// is 1), dZ3 = [H3 > 0] * dz * w_o, and per-workgroup partials of
+// dw_o = sum dz * H3 and db_o = sum dz over the workgroup's row range.
+__global__ void __launch_bounds__(kThreads) readout_bwd_kernel(int64_t R, uint32_t B, int64_t rows_per,
+                                                               const uint16_t* __restrict__ H,
+                                                               const float* __restrict__ Yhat,
+                                                               const float* __restrict__ g, const float* __restrict__ w_o,
+                                                               uint16_t* __restrict__ dZ, float* __restrict__ part)
+{
+    __shared__ float red[kThreads / 8][kHidden + 1];
+    const int sub = threadIdx.x & 7, grp = threadIdx.x >> 3;
+    float wv[8], acc[8], accb = 0.0f;
+    #pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        wv[i] = bf2f(f2bf(w_o[8 * sub + i]));
+        acc[i] = 0.0f;
+    }
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per;
+    const int64_t r1 = r0 + rows_per < R ? r0 + rows_per : R;
+    for (int64_t r = r0 + grp; r < r1; r += kThreads / 8) {
+        const float y = Yhat[r];
+        const float dz = g[r % B] * y * (1.0f - y);
+        float h[8];
+        unpack8(*(const u32x4*)(H + r * kHidden + 8 * sub), h);
+        u32x4 o;
+        float d[8];
+        #pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            d[i] = h[i] > 0.0f ? dz * wv[i] : 0.0f;
+            acc[i] = fmaf(dz, h[i], acc[i]);
+        }
+        #pragma unroll
+        for (int i = 0; i < 4; ++i) o[i] = pack2(d[2 * i], d[2 * i + 1]);
+        *(u32x4*)(dZ + r * kHidden + 8 * sub) = o;
+        accb += dz;
+    }
+    #pragma unroll
+    for (int i = 0; i < 8; ++i) red[grp][8 * sub + i] = acc[i];
+    if (sub == 0) red[grp][kHidden] = accb;
+    __syncthreads();
+    if (threadIdx.x <= kHidden) {
+        float s = 0.0f;
+        for (int j = 0; j < kThreads / 8; ++j) s += red[j][threadIdx.x];
+        part[(int64_t)blockIdx.x * (kHidden + 1) + threadIdx.x] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Adam (Kingma and Ba), bias-corrected, on fp32 master parameters.
+__global__ void adam_kernel(int64_t count, float* __restrict__ p, const float* __restrict__ grad, float* __restrict__ m,
+                            float* __restrict__ v, float lr, float beta1, float beta2, float eps, float corr1, float corr2)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+        const float gi = grad[i];
+        const float mi = beta1 * m[i] + (1.0f - beta1) * gi;
+        const float vi = beta2 * v[i] + (1.0f - beta2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        p[i] -= lr * (mi / corr1) / (sqrtf(vi / corr2) + eps);
+    }
+}
+
+}  // namespace imsim_mpnn

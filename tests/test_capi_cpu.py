@@ -1,5 +1,5 @@
 """Host-side checks of the C-ABI library that need no GPU: it loads, exports
-every function include/imsim.h declares, and its encoders and validation
+every function the headers under include/ declare, and its encoders and validation
 behave as the header states."""
 import ctypes
 import os
@@ -15,7 +15,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared_functions():
-    text = open(os.path.join(ROOT, "include", "imsim.h")).read()
+    text = "".join(open(os.path.join(ROOT, "include", h)).read()
+                   for h in sorted(os.listdir(os.path.join(ROOT, "include"))) if h.endswith(".h"))
     return sorted(set(re.findall(r"^\s*(?:const\s+)?[\w\s\*]+?\b(ims_\w+)\s*\(", text, flags=re.M)))
 
 

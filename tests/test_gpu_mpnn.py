@@ -1,0 +1,303 @@
+"""GPU spread estimator vs the FP64 reference (oracle/mpnn_ref.py).
+
+Per kernel: every internal tensor of a forward and backward is recomputed in
+fp64 from the GPU's own bf16 inputs of that step, so each kernel is checked
+alone (bf16 output: within one rounding of the fp64 value, plus fp32
+accumulation slack).  End to end: predictions and gradients against the fp64
+reference run with bf16-rounded weights and no intermediate rounding.
+"""
+import numpy as np
+import pytest
+
+from oracle import mpnn_ref as R
+import synth
+
+pytestmark = pytest.mark.gpu
+
+BF16_REL = 2.0 ** -8
+
+
+def _mods():
+    import torch
+
+    import paper_2404_17059_amd as ims
+    from paper_2404_17059_amd import mpnn
+    return torch, ims, mpnn
+
+
+def graph_case(n, seed, mean_degree=6.0):
+    g = synth.chung_lu_undirected(n, 2.3, mean_degree, seed=seed)
+    a = synth.weighted_cascade(g).astype(np.float32)
+    return g, a
+
+
+def random_sets(n, B, seed, max_size=12, deg=None):
+    rng = np.random.default_rng(seed)
+    sets = []
+    for b in range(B):
+        k = int(rng.integers(0, max_size + 1))
+        if deg is not None and b % 2:
+            p = (deg + 1.0) / (deg + 1.0).sum()
+            s = rng.choice(n, size=k, p=p)
+        else:
+            s = rng.integers(0, n, size=k)
+        sets.append(s.astype(np.uint32))
+    if B > 1:
+        sets[0] = np.array([], dtype=np.uint32)           # empty set
+        sets[1] = np.array([3, 3, 5], dtype=np.uint32)    # duplicates
+    return sets
+
+
+def params_for_test(seed):
+    rng = np.random.default_rng(seed)
+    p = rng.normal(0.0, 0.35, size=R.NPARAMS)
+    p[R.OFF["b0"]:R.OFF["b0"] + 64] += 0.2
+    p[R.OFF["bo"]] = -2.0
+    return p.astype(np.float32)
+
+
+def check_bf16(gpu, ref, scale, what, terms):
+    """gpu = bf16(fp32 sum of `terms` products) against the exact sum `ref`:
+    one bf16 rounding plus the worst-case fp32 summation error terms * 2^-24
+    of the sum of magnitudes `scale` (counted twice for the final rounding)."""
+    err = np.abs(gpu - ref)
+    bound = BF16_REL * np.abs(ref) + 2.0 * np.asarray(terms, dtype=np.float64) * 2.0 ** -24 * scale + 1e-30
+    bad = err > bound
+    assert not bad.any(), f"{what}: {bad.sum()} of {bad.size} outside one bf16 rounding; worst {err[bad].max()} (scale {scale.max() if np.ndim(scale) else scale})"
+
+
+def dense_ref(Xs, Xn, W, b):
+    Xcat = np.concatenate([Xs, Xn], axis=-1)
+    z = Xcat @ W + b
+    scale = np.abs(Xcat) @ np.abs(W) + np.abs(b)
+    return np.maximum(z, 0.0), scale
+
+
+def run_case(n, B, seed, check_backward=True):
+    torch, ims, mpnn = _mods()
+    g, a = graph_case(n, seed)
+    sets = random_sets(n, B, seed + 1, deg=g.outdeg().astype(np.float64))
+    p32 = params_for_test(seed + 2)
+    S = mpnn.Surrogate(n, g.offsets, g.indices, a, max_batch=max(B, 1))
+    params = torch.from_numpy(p32).cuda()
+    pred = S.forward(params, sets)
+    target_np = np.array([len(set(s.tolist())) + 5.0 * (i % 3) for i, s in enumerate(sets)], dtype=np.float32)
+    target = torch.from_numpy(target_np).cuda()
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    grads = S.backward(params, target, loss=loss) if check_backward else None
+    torch.cuda.synchronize()
+    return torch, mpnn, g, a, sets, p32, S, params, pred, target_np, grads, loss
+
+
+@pytest.mark.parametrize("n,B,seed", [(37, 3, 10), (300, 5, 20), (2000, 16, 30), (20000, 8, 40)])
+def test_each_kernel_against_fp64_on_gpu_inputs(n, B, seed):
+    torch, mpnn, g, a, sets, p32, S, params, pred, target, grads, loss = run_case(n, B, seed)
+    P = R.unpack(p32.astype(np.float64))
+    Wb = {k: R.bf16_round(P[k].astype(np.float32)) for k in ("W0", "W1", "W2", "wo")}
+    in_off, src, w = R.in_csr(n, g.offsets, g.indices, a.astype(np.float64))
+    feat = R.features(n, g.offsets, g.indices, a)
+
+    indeg = (np.diff(in_off) + 1)[:, None, None]
+    outdeg = (np.diff(g.offsets) + 2)[:, None, None]
+    X0 = S.fetch("X0")
+    np.testing.assert_array_equal(X0, R.bf16_round(R.input_features(n, feat, sets)))
+    H = [X0]
+    M = []
+    for layer in range(3):
+        Mg = S.fetch(f"M{layer}")
+        Mr = R.aggregate(n, in_off, src, w, H[layer])
+        Ms = R.aggregate(n, in_off, src, w, np.abs(H[layer]))
+        check_bf16(Mg, Mr, Ms, f"M{layer}", indeg)
+        M.append(Mg)
+        Hg = S.fetch(f"H{layer + 1}")
+        Hr, sc = dense_ref(H[layer], Mg, Wb[f"W{layer}"], P[f"b{layer}"])
+        check_bf16(Hg, Hr, sc, f"H{layer + 1}", 2 * H[layer].shape[2] + 1)
+        H.append(Hg)
+    Y = S.fetch("YHAT")
+    z = H[3] @ Wb["wo"] + P["bo"][0]
+    with np.errstate(over="ignore"):
+        Yr = np.where(X0[:, :, 0] != 0, 1.0, 1.0 / (1.0 + np.exp(-z)))
+    np.testing.assert_allclose(Y, Yr, rtol=2e-6, atol=2e-6)
+    np.testing.assert_allclose(pred.cpu().numpy(), Y.sum(axis=0), rtol=1e-5)
+
+    # backward, kernel by kernel
+    predg = pred.cpu().numpy().astype(np.float32)
+    d = (predg - target) * np.float32(1.0 / n)
+    gb = (2.0 * d * np.float32(1.0 / n) / np.float32(B)).astype(np.float64)
+    np.testing.assert_allclose(loss.cpu().numpy()[0], np.mean(d.astype(np.float64) ** 2), rtol=1e-5)
+    dz = gb[None, :] * Y * (1.0 - Y)
+    dZ3 = S.fetch("DZ3")
+    check_bf16(dZ3, (H[3] > 0) * dz[:, :, None] * Wb["wo"], np.abs(dz[:, :, None] * Wb["wo"]), "DZ3", 1)
+    gr = grads.cpu().numpy().astype(np.float64)
+    G = R.unpack(gr)
+    sc_wo = np.einsum("vb,vbc->c", np.abs(dz), H[3])
+    assert np.all(np.abs(G["wo"] - np.einsum("vb,vbc->c", dz, H[3])) <= 1e-4 * sc_wo + 1e-30)
+    assert abs(G["bo"][0] - dz.sum()) <= 1e-4 * np.abs(dz).sum() + 1e-30
+    dZ = {3: dZ3}
+    for layer in (2, 1, 0):
+        Xcat = np.concatenate([H[layer], M[layer]], axis=2)
+        dZl = dZ[layer + 1]
+        Wr = np.einsum("vbk,vbc->kc", Xcat, dZl)
+        Ws = np.einsum("vbk,vbc->kc", np.abs(Xcat), np.abs(dZl))
+        assert np.all(np.abs(G[f"W{layer}"] - Wr) <= 1e-4 * Ws + 1e-30), f"dW{layer}"
+        br, bs = dZl.sum(axis=(0, 1)), np.abs(dZl).sum(axis=(0, 1))
+        assert np.all(np.abs(G[f"b{layer}"] - br) <= 1e-4 * bs + 1e-30), f"db{layer}"
+        if layer == 0:
+            break
+        dX = dZl @ Wb[f"W{layer}"].T
+        dXs = np.abs(dZl) @ np.abs(Wb[f"W{layer}"]).T
+        dH, dM = S.fetch(f"DH{layer}"), S.fetch(f"DM{layer}")
+        check_bf16(dH, dX[:, :, :64], dXs[:, :, :64], f"DH{layer}", 65)
+        check_bf16(dM, dX[:, :, 64:], dXs[:, :, 64:], f"DM{layer}", 65)
+        zr = (H[layer] > 0) * (dH + R.aggregate_transpose(n, in_off, src, w, dM))
+        zs = np.abs(dH) + R.aggregate_transpose(n, in_off, src, w, np.abs(dM))
+        dZg = S.fetch(f"DZ{layer}")
+        check_bf16(dZg, zr, zs, f"DZ{layer}", outdeg)
+        dZ[layer] = dZg
+    S.close()
+
+
+def cosine(x, y):
+    return float(x @ y / (np.linalg.norm(x) * np.linalg.norm(y)))
+
+
+@pytest.mark.parametrize("n,B,seed", [(300, 5, 50), (3000, 12, 60)])
+def test_end_to_end_against_fp64_reference(n, B, seed):
+    torch, mpnn, g, a, sets, p32, S, params, pred, target, grads, loss = run_case(n, B, seed)
+    fwd = R.forward(p32.astype(np.float64), n, g.offsets, g.indices, a, [s.tolist() for s in sets], bf16_weights=True)
+    pr = fwd["pred"]
+    np.testing.assert_allclose(pred.cpu().numpy(), pr, rtol=1e-2)
+    gref, Lref = R.backward(fwd, target)
+    gg = grads.cpu().numpy().astype(np.float64)
+    assert abs(loss.cpu().numpy()[0] - Lref) <= 3e-2 * Lref + 1e-12
+    Gr, Gg = R.unpack(gref), R.unpack(gg)
+    for k in ("W0", "b0", "W1", "b1", "W2", "b2", "wo", "bo"):
+        x, y = Gg[k].ravel(), Gr[k].ravel()
+        if np.linalg.norm(y) == 0:
+            continue
+        rel = np.linalg.norm(x - y) / np.linalg.norm(y)
+        assert rel < 3e-2, (k, rel)
+        if y.size > 1:
+            assert cosine(x, y) > 0.999, (k, cosine(x, y))
+    S.close()
+
+
+def test_deterministic_and_batch_independent():
+    torch, ims, mpnn = _mods()
+    n = 1500
+    g, a = graph_case(n, 70)
+    sets = random_sets(n, 6, 71)
+    params = torch.from_numpy(params_for_test(72)).cuda()
+    S = mpnn.Surrogate(n, g.offsets, g.indices, a, max_batch=8)
+    target = torch.arange(6, dtype=torch.float32, device="cuda") * 3
+    p1 = S.forward(params, sets).clone()
+    g1 = S.backward(params, target).clone()
+    p2 = S.forward(params, sets).clone()
+    g2 = S.backward(params, target).clone()
+    assert torch.equal(p1, p2) and torch.equal(g1, g2)
+    # a set's prediction does not depend on its batch companions
+    for b in range(6):
+        pb = S.forward(params, [sets[b]]).cpu().numpy()[0]
+        assert abs(pb - p1[b].item()) <= 1e-5 * abs(pb), b
+    S.close()
+
+
+def test_argument_errors():
+    torch, ims, mpnn = _mods()
+    g, a = graph_case(50, 80)
+    S = mpnn.Surrogate(50, g.offsets, g.indices, a, max_batch=2)
+    params = torch.zeros(mpnn.NPARAMS, dtype=torch.float32, device="cuda")
+    with pytest.raises(ims.ImsError) as e:
+        S.forward(params, [[50]])
+    assert e.value.code == -4
+    with pytest.raises(ims.ImsError) as e:
+        S.forward(params, [[1], [2], [3]])
+    assert e.value.code == -1
+    with pytest.raises(ims.ImsError):
+        mpnn.Surrogate(50, g.offsets, g.indices, a, max_batch=0)
+    # all-zero weights: every non-seed node predicts sigmoid(0) = 1/2
+    p = S.forward(params, [[1, 2], []]).cpu().numpy()
+    np.testing.assert_allclose(p, [2 + 48 * 0.5, 50 * 0.5], rtol=1e-6)
+    S.close()
+
+
+def test_adam_step_matches_formula():
+    torch, ims, mpnn = _mods()
+    rng = np.random.default_rng(90)
+    p0 = rng.normal(size=1000).astype(np.float32)
+    gr = rng.normal(size=1000).astype(np.float32)
+    m0 = rng.normal(size=1000).astype(np.float32) * 0.1
+    v0 = np.abs(rng.normal(size=1000)).astype(np.float32) * 0.01
+    P, Gt, Mt, Vt = (torch.from_numpy(x.copy()).cuda() for x in (p0, gr, m0, v0))
+    mpnn.adam_step(P, Gt, Mt, Vt, lr=1e-2, step=3, beta1=0.9, beta2=0.999, eps=1e-8)
+    # the kernel's coefficients are fp32: 1 - 0.999f is not 0.001
+    b1, b2 = (float(np.float32(x)) for x in (0.9, 0.999))
+    c1, c2 = 1.0 - b1, 1.0 - b2
+    g64, m64, v64 = (x.astype(np.float64) for x in (gr, m0, v0))
+    m = b1 * m64 + c1 * g64
+    v = b2 * v64 + c2 * g64 * g64
+    step = 1e-2 * (m / (1 - 0.9 ** 3)) / (np.sqrt(v / (1 - 0.999 ** 3)) + 1e-8)
+    p = p0 - step
+    tol = 2.0 ** -22  # a few fp32 roundings of each term
+    assert np.all(np.abs(Mt.cpu().numpy() - m) <= tol * (np.abs(b1 * m64) + np.abs(c1 * g64)))
+    assert np.all(np.abs(Vt.cpu().numpy() - v) <= tol * v)
+    assert np.all(np.abs(P.cpu().numpy() - p) <= 1e-5 * np.abs(step) + tol * np.abs(p0))
+
+
+def test_training_overfits_eight_sets():
+    torch, ims, mpnn = _mods()
+    n = 400
+    g, a = graph_case(n, 100)
+    sets = random_sets(n, 8, 101)
+    sets[0] = np.array([7], dtype=np.uint32)
+    target = torch.tensor([len(set(s.tolist())) * 4.0 + 10.0 for s in sets], dtype=torch.float32, device="cuda")
+    S = mpnn.Surrogate(n, g.offsets, g.indices, a, max_batch=8)
+    params = torch.from_numpy(mpnn.init_params(5)).cuda()
+    m, v = torch.zeros_like(params), torch.zeros_like(params)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    first = None
+    for step in range(1, 601):
+        S.forward(params, sets)
+        grads = S.backward(params, target, loss=loss)
+        if first is None:
+            first = loss.item()
+        mpnn.adam_step(params, grads, m, v, lr=3e-3, step=step)
+    S.forward(params, sets)
+    S.backward(params, target, loss=loss)
+    assert loss.item() < 1e-3 * first, (first, loss.item())
+    S.close()
+
+
+def test_full_size_graph_sampled_rows():
+    """Undirected Chung-Lu n = 200,000 (mean degree 10, exponent 2.3), weighted
+    cascade arcs, 8 sets of 1-50 nodes: the aggregation and dense kernels on
+    1,000 sampled nodes, each recomputed from the GPU's inputs."""
+    torch, ims, mpnn = _mods()
+    g, wc = synth.chung_lu_wc_200k()
+    n = g.n
+    a = wc.astype(np.float32)
+    rng = np.random.default_rng(110)
+    sets = [rng.integers(0, n, size=int(rng.integers(1, 51))).astype(np.uint32) for _ in range(8)]
+    S = mpnn.Surrogate(n, g.offsets, g.indices, a, max_batch=8)
+    p32 = params_for_test(111)
+    params = torch.from_numpy(p32).cuda()
+    pred = S.forward(params, sets)
+    P = R.unpack(p32.astype(np.float64))
+    Wb = {k: R.bf16_round(P[k].astype(np.float32)) for k in ("W0", "W1", "W2")}
+    in_off, src, w = R.in_csr(n, g.offsets, g.indices, a.astype(np.float64))
+    nodes = np.sort(rng.choice(n, 1000, replace=False))
+    for layer in range(3):
+        Hin = S.fetch("X0" if layer == 0 else f"H{layer}")
+        Mg = S.fetch(f"M{layer}", nodes)
+        for i, v in enumerate(nodes):
+            e0, e1 = in_off[v], in_off[v + 1]
+            ref = (w[e0:e1, None, None] * Hin[src[e0:e1]]).sum(axis=0)
+            sc = (w[e0:e1, None, None] * np.abs(Hin[src[e0:e1]])).sum(axis=0)
+            check_bf16(Mg[i], ref, sc, f"M{layer} node {v}", e1 - e0 + 1)
+        Hg = S.fetch(f"H{layer + 1}", nodes)
+        Hr, sc = dense_ref(Hin[nodes], Mg, Wb[f"W{layer}"], P[f"b{layer}"])
+        check_bf16(Hg, Hr, sc, f"H{layer + 1}", 2 * Hin.shape[2] + 1)
+        del Hin
+    Y = S.fetch("YHAT")
+    np.testing.assert_allclose(pred.cpu().numpy(), Y.sum(axis=0), rtol=1e-5)
+    S.close()
