@@ -27,15 +27,25 @@ def _sigma_of(graph: Graph, base: list[int], extra: list[int], R: int, rng_seed:
     return out
 
 
-def greedy(graph: Graph, k: int, R: int, rng_seed: int, candidates=None, chunk: int = 4096) -> dict:
+def _evaluator(graph, R: int, rng_seed: int, chunk: int):
+    """graph: a Graph (Monte Carlo on the GPU) or a callable
+    (base, extra) -> totals standing in for it."""
+    if callable(graph) and not isinstance(graph, Graph):
+        return graph
+    return lambda base, extra: _sigma_of(graph, base, extra, R, rng_seed, chunk)
+
+
+def greedy(graph, k: int, R: int, rng_seed: int, candidates=None, chunk: int = 4096, n: int | None = None) -> dict:
     """Plain greedy: every round evaluates sigma(S + v) for every candidate."""
-    cand = list(range(graph.n)) if candidates is None else [int(c) for c in candidates]
+    n = graph.n if n is None else n
+    sigma_of = _evaluator(graph, R, rng_seed, chunk)
+    cand = list(range(n)) if candidates is None else [int(c) for c in candidates]
     S: list[int] = []
     cur = 0
     evals = 0
     for _ in range(k):
         rest = [v for v in cand if v not in set(S)]
-        tot = _sigma_of(graph, S, rest, R, rng_seed, chunk)
+        tot = sigma_of(S, rest)
         evals += len(rest)
         best = int(np.argmax(tot))  # first maximum = smallest id among ties (rest is sorted)
         S.append(rest[best])
@@ -43,12 +53,15 @@ def greedy(graph: Graph, k: int, R: int, rng_seed: int, candidates=None, chunk: 
     return {"seeds": S, "sigma": cur / R, "evaluations": evals}
 
 
-def celf(graph: Graph, k: int, R: int, rng_seed: int, candidates=None, chunk: int = 4096, batch: int = 64) -> dict:
+def celf(graph, k: int, R: int, rng_seed: int, candidates=None, chunk: int = 4096, batch: int = 64,
+         n: int | None = None) -> dict:
     """Lazy greedy.  The heap holds (-gain upper bound, node, round evaluated);
     stale tops are re-evaluated `batch` at a time against the current S."""
     t0 = time.perf_counter()
-    cand = sorted(range(graph.n) if candidates is None else {int(c) for c in candidates})
-    first = _sigma_of(graph, [], cand, R, rng_seed, chunk)
+    n = graph.n if n is None else n
+    sigma_of = _evaluator(graph, R, rng_seed, chunk)
+    cand = sorted(range(n) if candidates is None else {int(c) for c in candidates})
+    first = sigma_of([], cand)
     evals = len(cand)
     heap = [(-int(t), v, 0) for t, v in zip(first, cand)]
     heapq.heapify(heap)
@@ -66,7 +79,7 @@ def celf(graph: Graph, k: int, R: int, rng_seed: int, candidates=None, chunk: in
         while heap and heap[0][2] != len(S) and len(stale) < batch:
             stale.append(heapq.heappop(heap))
         vs = [v for _, v, _ in stale]
-        tot = _sigma_of(graph, S, vs, R, rng_seed, chunk)
+        tot = sigma_of(S, vs)
         evals += len(vs)
         for v, t in zip(vs, tot):
             heapq.heappush(heap, (-(int(t) - cur_total), v, len(S)))

@@ -180,22 +180,31 @@ def chung_lu_undirected(n: int, gamma: float, mean_degree: float, seed: int) -> 
     return from_arcs(n, np.concatenate([lo, hi]), np.concatenate([hi, lo]))
 
 
-def random_regular(n: int, d: int, seed: int, max_tries: int = 1000) -> Graph:
-    """Random d-regular simple undirected graph by repeated configuration
-    pairing (rejecting self-loops and multi-edges), both arcs kept."""
+def random_regular(n: int, d: int, seed: int, max_rounds: int = 10000) -> Graph:
+    """Random d-regular simple undirected graph, both arcs kept: one
+    configuration-model pairing of the n*d stubs, then every self-loop or
+    repeated edge is switched with a random edge (a degree-preserving swap of
+    endpoints) until the graph is simple."""
     rng = np.random.Generator(np.random.PCG64(seed))
     if (n * d) % 2:
         raise ValueError("n*d must be even")
-    for _ in range(max_tries):
-        stubs = rng.permutation(np.repeat(np.arange(n, dtype=np.int64), d))
-        a, b = stubs[0::2], stubs[1::2]
-        if np.any(a == b):
-            continue
+    stubs = rng.permutation(np.repeat(np.arange(n, dtype=np.int64), d))
+    a, b = stubs[0::2].copy(), stubs[1::2].copy()
+    for _ in range(max_rounds):
         lo, hi = np.minimum(a, b), np.maximum(a, b)
-        if np.unique(lo * n + hi).shape[0] != lo.shape[0]:
-            continue
-        return from_arcs(n, np.concatenate([lo, hi]), np.concatenate([hi, lo]))
-    raise RuntimeError("random_regular: no simple pairing found")
+        _, first = np.unique(lo * n + hi, return_index=True)
+        repeated = np.ones(a.shape[0], dtype=bool)
+        repeated[first] = False
+        bad = np.flatnonzero((a == b) | repeated)
+        if bad.size == 0:
+            return from_arcs(n, np.concatenate([lo, hi]), np.concatenate([hi, lo]))
+        for i in bad:
+            j = int(rng.integers(0, a.shape[0]))
+            if rng.random() < 0.5:
+                a[i], b[j] = b[j], a[i]
+            else:
+                a[i], a[j] = a[j], a[i]
+    raise RuntimeError("random_regular: switching did not reach a simple graph")
 
 
 def watts_strogatz(n: int, k: int, p: float, seed: int) -> Graph:
