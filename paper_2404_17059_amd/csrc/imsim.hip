@@ -436,14 +436,16 @@ int ims_simulate(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_t
     // LT grid shape: threshold prefix table when it fits the budget
     const int test_flags = opts ? opts->test_flags : 0;
     // LT grid shape threshold form: count thresholds (equal in-weights, 64 B
-    // per node-word), full hashes (256 B), or hashes drawn in the kernel
+    // per node-word, words padded to whole groups), full hashes (256 B), or
+    // hashes drawn in the kernel
     int lt_mode = 0;
+    const uint64_t kmin_bytes = (uint64_t)g->n * ((W + imsim::kRowWords - 1) / imsim::kRowWords) * 64ull * imsim::kRowWords;
     if (shape == 2 && g->model == IMS_MODEL_LT && !(test_flags & 1)) {
-        if (g->lt_uniform && !(test_flags & 4) && cells * 64 <= kThresholdTableBudget && !(test_flags & 8)) lt_mode = 2;
+        if (g->lt_uniform && !(test_flags & 4) && kmin_bytes <= kThresholdTableBudget && !(test_flags & 8)) lt_mode = 2;
         else if (cells * 256 <= kThresholdTableBudget) lt_mode = 1;
     }
     const bool use_table = lt_mode != 0;
-    if (use_table && (rc = ensure_buf(g, g->thp, cells * (lt_mode == 2 ? 64 : 256), false))) return rc;
+    if (use_table && (rc = ensure_buf(g, g->thp, lt_mode == 2 ? kmin_bytes : cells * 256, false))) return rc;
     if (g->seeds_cap < sv.size() || !g->d_seeds) {
         dev_free(g->d_seeds);
         dev_free(g->d_seed_pre);

@@ -78,6 +78,12 @@ struct ims_mpnn {
     uint32_t* out_dst = nullptr;
     float* out_w = nullptr;
     float* feat = nullptr;          // [n][3]
+    // aggregation work items of the in-CSR (0, forward) and out-CSR (1, backward)
+    SpmmItem* items[2] = {nullptr, nullptr};
+    uint32_t n_items[2] = {0, 0};
+    uint32_t* fin[2] = {nullptr, nullptr};
+    uint32_t n_fin[2] = {0, 0};
+    float* seg_partial = nullptr;   // [slots][max_batch * 64]
     uint16_t* t[IMS_MPNN_T_COUNT] = {};
     float* part = nullptr;          // per-workgroup partial sums
     int64_t part_floats = 0;
@@ -99,7 +105,37 @@ void destroy(ims_mpnn* p)
         if (q) (void)hipFree(q);
     for (uint16_t* q : p->t)
         if (q) (void)hipFree(q);
+    for (int k = 0; k < 2; ++k) {
+        if (p->items[k]) (void)hipFree(p->items[k]);
+        if (p->fin[k]) (void)hipFree(p->fin[k]);
+    }
+    if (p->seg_partial) (void)hipFree(p->seg_partial);
     delete p;
+}
+
+// Work items of one CSR: rows longer than kSegArcs become segments with
+// partial slots (listed first, they are the long-running items), the rest
+// one direct item each.
+void build_items(int64_t n, const int64_t* off, std::vector<SpmmItem>& items, std::vector<uint32_t>& fin, uint32_t& slots)
+{
+    items.clear();
+    fin.clear();
+    slots = 0;
+    for (int64_t v = 0; v < n; ++v) {
+        const int64_t deg = off[v + 1] - off[v];
+        if (deg <= (int64_t)kSegArcs) continue;
+        fin.push_back((uint32_t)v);
+        fin.push_back(slots);
+        uint32_t k = 0;
+        for (int64_t e = off[v]; e < off[v + 1]; e += kSegArcs, ++k)
+            items.push_back(SpmmItem{(uint32_t)v, slots + k, (uint32_t)e, (uint32_t)std::min<int64_t>(kSegArcs, off[v + 1] - e)});
+        fin.push_back(k);
+        slots += k;
+    }
+    for (int64_t v = 0; v < n; ++v) {
+        const int64_t deg = off[v + 1] - off[v];
+        if (deg <= (int64_t)kSegArcs) items.push_back(SpmmItem{(uint32_t)v, kDirect, (uint32_t)off[v], (uint32_t)deg});
+    }
 }
 
 // workgroups of the weight-gradient kernel and its rows per workgroup
@@ -127,16 +163,26 @@ int dense_forward(ims_mpnn* p, int64_t R, const uint16_t* Xs, const uint16_t* Xn
 int spmm(ims_mpnn* p, bool backward, uint32_t C, const uint16_t* X, uint16_t* Y, const uint16_t* add,
          const uint16_t* relu_of, hipStream_t s)
 {
+    const int k = backward ? 1 : 0;
     const uint32_t nc = C / 8;
     const int64_t per_block = nc >= (uint32_t)kThreads ? 1 : kThreads / nc;
-    const unsigned grid = grid_for(p->n, per_block, INT32_MAX);
+    const unsigned grid = grid_for(p->n_items[k], per_block, INT32_MAX);
     if (backward)
-        hipLaunchKernelGGL(spmm_kernel<true>, dim3(grid), dim3(kThreads), 0, s, p->n, C, p->out_off, p->out_dst, p->out_w,
-                           X, Y, add, relu_of);
+        hipLaunchKernelGGL(spmm_kernel<true>, dim3(grid), dim3(kThreads), 0, s, p->n_items[1], C, (const SpmmItem*)p->items[1],
+                           (const uint32_t*)p->out_dst, (const float*)p->out_w, X, Y, add, relu_of, p->seg_partial);
     else
-        hipLaunchKernelGGL(spmm_kernel<false>, dim3(grid), dim3(kThreads), 0, s, p->n, C, p->in_off, p->in_src, p->in_w,
-                           X, Y, nullptr, nullptr);
+        hipLaunchKernelGGL(spmm_kernel<false>, dim3(grid), dim3(kThreads), 0, s, p->n_items[0], C, (const SpmmItem*)p->items[0],
+                           (const uint32_t*)p->in_src, (const float*)p->in_w, X, Y, nullptr, nullptr, p->seg_partial);
     MP_HIP(hipGetLastError());
+    if (p->n_fin[k]) {
+        if (backward)
+            hipLaunchKernelGGL(spmm_finish_kernel<true>, dim3(p->n_fin[1]), dim3(kThreads), 0, s, C, (const uint32_t*)p->fin[1],
+                               (const float*)p->seg_partial, Y, add, relu_of);
+        else
+            hipLaunchKernelGGL(spmm_finish_kernel<false>, dim3(p->n_fin[0]), dim3(kThreads), 0, s, C, (const uint32_t*)p->fin[0],
+                               (const float*)p->seg_partial, Y, nullptr, nullptr);
+        MP_HIP(hipGetLastError());
+    }
     return IMS_OK;
 }
 
@@ -176,7 +222,7 @@ int ims_mpnn_create(int64_t n, int64_t m, const int64_t* offsets, const uint32_t
     *out = nullptr;
     if (n < 1 || m < 0 || !offsets || (m > 0 && (!indices || !arc_weight)))
         return fail(IMS_E_INVALID_ARG, "ims_mpnn_create: bad n, m or NULL arrays");
-    if (n >= (int64_t)1 << 32) return fail(IMS_E_UNSUPPORTED, "ims_mpnn_create: n >= 2^32");
+    if (n >= (int64_t)1 << 32 || m >= (int64_t)1 << 32) return fail(IMS_E_UNSUPPORTED, "ims_mpnn_create: n or m >= 2^32");
     if (max_batch < 1 || max_batch > IMS_MPNN_MAX_BATCH)
         return fail(IMS_E_INVALID_ARG, "ims_mpnn_create: max_batch must be 1..%d", IMS_MPNN_MAX_BATCH);
     int rc = ims_validate_csr(n, m, offsets, indices);
@@ -208,6 +254,12 @@ int ims_mpnn_create(int64_t n, int64_t m, const int64_t* offsets, const uint32_t
         feat[3 * v + 2] = (float)sum;
     }
 
+    std::vector<SpmmItem> items[2];
+    std::vector<uint32_t> fin[2];
+    uint32_t slots[2];
+    build_items(n, in_off.data(), items[0], fin[0], slots[0]);
+    build_items(n, offsets, items[1], fin[1], slots[1]);
+
     ims_mpnn* p = new (std::nothrow) ims_mpnn;
     if (!p) return fail(IMS_E_OOM, "ims_mpnn_create: host allocation");
     p->n = n;
@@ -236,6 +288,13 @@ int ims_mpnn_create(int64_t n, int64_t m, const int64_t* offsets, const uint32_t
     rc = rc ? rc : alloc(&p->pred, max_batch);
     rc = rc ? rc : alloc(&p->g, max_batch);
     for (int id = 0; id < IMS_MPNN_T_COUNT && !rc; ++id) rc = alloc(&p->t[id], rows * tensor_width(id));
+    for (int k = 0; k < 2 && !rc; ++k) {
+        p->n_items[k] = (uint32_t)items[k].size();
+        p->n_fin[k] = (uint32_t)(fin[k].size() / 3);
+        rc = alloc(&p->items[k], items[k].size());
+        rc = rc ? rc : alloc(&p->fin[k], fin[k].size());
+    }
+    rc = rc ? rc : alloc(&p->seg_partial, (uint64_t)std::max(slots[0], slots[1]) * max_batch * kHidden);
     if (rc) {
         destroy(p);
         return rc;
@@ -249,6 +308,12 @@ int ims_mpnn_create(int64_t n, int64_t m, const int64_t* offsets, const uint32_t
         e = e != hipSuccess ? e : hipMemcpy(p->in_w, in_w.data(), m * 4, hipMemcpyHostToDevice);
         e = e != hipSuccess ? e : hipMemcpy(p->out_dst, indices, m * 4, hipMemcpyHostToDevice);
         e = e != hipSuccess ? e : hipMemcpy(p->out_w, arc_weight, m * 4, hipMemcpyHostToDevice);
+    }
+    for (int k = 0; k < 2; ++k) {
+        if (!items[k].empty())
+            e = e != hipSuccess ? e : hipMemcpy(p->items[k], items[k].data(), items[k].size() * sizeof(SpmmItem), hipMemcpyHostToDevice);
+        if (!fin[k].empty())
+            e = e != hipSuccess ? e : hipMemcpy(p->fin[k], fin[k].data(), fin[k].size() * 4, hipMemcpyHostToDevice);
     }
     if (e != hipSuccess) {
         destroy(p);

@@ -93,42 +93,76 @@ __global__ void seed_scatter_kernel(uint32_t n_sets, uint32_t B, const uint32_t*
 
 // ---------------------------------------------------------------------------
 // Sparse aggregation.  Y[v] = sum over arcs e of the CSR row of v of
-// w[e] * X[nbr[e]], where a node row holds C = B*D bf16 values.  A lane owns
-// eight consecutive values (16 bytes); nodes with C/8 < 256 chunks share a
-// workgroup.  Forward: CSR = arcs into v, Y = M.  Backward: CSR = arcs out of
-// v, and the epilogue adds `add` and zeroes where `relu_of` <= 0 (the ReLU of
-// the layer below), producing that layer's pre-activation gradient.
+// w[e] * X[nbr[e]], where a node row holds C = B*D bf16 values.  Forward: CSR
+// = arcs into v, Y = M.  Backward: CSR = arcs out of v, and the epilogue adds
+// `add` and zeroes where `relu_of` <= 0 (the ReLU of the layer below),
+// producing that layer's pre-activation gradient.
+//
+// Work items are row segments of at most kSegArcs arcs, so a hub's row is
+// spread over many workgroups: a node with a short row is one item that
+// writes its output row; a long row's segments write fp32 partial rows to
+// slots that a second kernel sums in slot order.  A lane owns eight
+// consecutive values (16 bytes); items with C/8 < 256 chunks share a
+// workgroup.
+
+constexpr uint32_t kSegArcs = 256;
+constexpr uint32_t kDirect = 0xFFFFFFFFu;
+
+struct SpmmItem {
+    uint32_t node;  // output row
+    uint32_t slot;  // kDirect, or the partial row this segment writes
+    uint32_t e0;    // first arc
+    uint32_t len;   // arcs (<= kSegArcs for segments of split rows)
+};
 
 template <bool kBackward>
-__global__ void __launch_bounds__(kThreads) spmm_kernel(int64_t n, uint32_t C, const int64_t* __restrict__ off,
+__device__ __forceinline__ void spmm_store(float* acc, uint64_t o, uint16_t* __restrict__ Y, const uint16_t* __restrict__ add,
+                                           const uint16_t* __restrict__ relu_of)
+{
+    if constexpr (kBackward) {
+        float d[8], h[8];
+        unpack8(*(const u32x4*)(add + o), d);
+        unpack8(*(const u32x4*)(relu_of + o), h);
+        #pragma unroll
+        for (int i = 0; i < 8; ++i) acc[i] = h[i] > 0.0f ? acc[i] + d[i] : 0.0f;
+    }
+    u32x4 out;
+    #pragma unroll
+    for (int i = 0; i < 4; ++i) out[i] = pack2(acc[2 * i], acc[2 * i + 1]);
+    *(u32x4*)(Y + o) = out;
+}
+
+template <bool kBackward>
+__global__ void __launch_bounds__(kThreads) spmm_kernel(uint32_t n_items, uint32_t C, const SpmmItem* __restrict__ items,
                                                         const uint32_t* __restrict__ nbr, const float* __restrict__ w,
                                                         const uint16_t* __restrict__ X, uint16_t* __restrict__ Y,
                                                         const uint16_t* __restrict__ add,
-                                                        const uint16_t* __restrict__ relu_of)
+                                                        const uint16_t* __restrict__ relu_of, float* __restrict__ partial)
 {
     const uint32_t nc = C / 8;
     const uint32_t per_block = nc >= kThreads ? 1u : kThreads / nc;
     const uint32_t local = nc >= kThreads ? 0u : threadIdx.x / nc;
-    const int64_t v = (int64_t)blockIdx.x * per_block + local;
-    if (local >= per_block || v >= n) return;
-    const int64_t e0 = off[v], e1 = off[v + 1];
+    const uint64_t it = (uint64_t)blockIdx.x * per_block + local;
+    if (local >= per_block || it >= n_items) return;
+    const SpmmItem I = items[it];
+    const uint64_t e0 = I.e0, e1 = e0 + I.len;
     const uint32_t step = nc >= kThreads ? kThreads : nc;
     for (uint32_t j = nc >= kThreads ? threadIdx.x : threadIdx.x % nc; j < nc; j += step) {
         float acc[8];
         #pragma unroll
         for (int i = 0; i < 8; ++i) acc[i] = 0.0f;
-        int64_t e = e0;
-        for (; e + 4 <= e1; e += 4) {
-            u32x4 r[4];
-            float a[4];
+        uint64_t e = e0;
+        for (; e + 8 <= e1; e += 8) {
+            u32x4 r[8];
+            float a[8];
             #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < 8; ++q) {
                 const uint32_t u = nbr[e + q];
                 a[q] = w[e + q];
                 r[q] = *(const u32x4*)(X + (uint64_t)u * C + (uint64_t)j * 8);
             }
             #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < 8; ++q) {
                 float f[8];
                 unpack8(r[q], f);
                 #pragma unroll
@@ -144,18 +178,39 @@ __global__ void __launch_bounds__(kThreads) spmm_kernel(int64_t n, uint32_t C, c
             #pragma unroll
             for (int i = 0; i < 8; ++i) acc[i] = fmaf(a, f[i], acc[i]);
         }
-        const uint64_t o = (uint64_t)v * C + (uint64_t)j * 8;
-        if constexpr (kBackward) {
-            float d[8], h[8];
-            unpack8(*(const u32x4*)(add + o), d);
-            unpack8(*(const u32x4*)(relu_of + o), h);
-            #pragma unroll
-            for (int i = 0; i < 8; ++i) acc[i] = h[i] > 0.0f ? acc[i] + d[i] : 0.0f;
+        if (I.slot != kDirect) {
+            floatx4* dst = (floatx4*)(partial + (uint64_t)I.slot * C + (uint64_t)j * 8);
+            dst[0] = floatx4{acc[0], acc[1], acc[2], acc[3]};
+            dst[1] = floatx4{acc[4], acc[5], acc[6], acc[7]};
+            continue;
         }
-        u32x4 out;
+        spmm_store<kBackward>(acc, (uint64_t)I.node * C + (uint64_t)j * 8, Y, add, relu_of);
+    }
+}
+
+// Rows split into segments: fin[3k .. 3k+2] = (node, first slot, slots);
+// one workgroup per row sums its partial rows in slot order.
+template <bool kBackward>
+__global__ void __launch_bounds__(kThreads) spmm_finish_kernel(uint32_t C, const uint32_t* __restrict__ fin,
+                                                               const float* __restrict__ partial, uint16_t* __restrict__ Y,
+                                                               const uint16_t* __restrict__ add,
+                                                               const uint16_t* __restrict__ relu_of)
+{
+    const uint32_t node = fin[3 * blockIdx.x], slot0 = fin[3 * blockIdx.x + 1], slots = fin[3 * blockIdx.x + 2];
+    for (uint32_t j = threadIdx.x; j < C / 8; j += kThreads) {
+        float acc[8];
         #pragma unroll
-        for (int i = 0; i < 4; ++i) out[i] = pack2(acc[2 * i], acc[2 * i + 1]);
-        *(u32x4*)(Y + o) = out;
+        for (int i = 0; i < 8; ++i) acc[i] = 0.0f;
+        for (uint32_t k = 0; k < slots; ++k) {
+            const floatx4* src = (const floatx4*)(partial + (uint64_t)(slot0 + k) * C + (uint64_t)j * 8);
+            const floatx4 p0 = src[0], p1 = src[1];
+            #pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                acc[i] += p0[i];
+                acc[4 + i] += p1[i];
+            }
+        }
+        spmm_store<kBackward>(acc, (uint64_t)node * C + (uint64_t)j * 8, Y, add, relu_of);
     }
 }
 

@@ -628,30 +628,62 @@ __global__ __launch_bounds__(kBlock) void ltg_table_kernel(SimParams P, uint32_t
     }
 }
 
-// Count-threshold table (equal in-weights): kmin[(v*W + w)*64 + b] =
-// min(255, floor(H(seed, LT, 64w + b, v) / w_v) + 1): with c active in-arc
-// pieces of weight w_v, c * w_v > h exactly when c >= floor(h / w_v) + 1.
+// Count-threshold table (equal in-weights).  With c active in-arc pieces of
+// weight w_v, c * w_v > h exactly when c >= floor(h / w_v) + 1, so the table
+// holds k = min(255, floor(H(seed, LT, t, v) / w_v) + 1) per (node, trial).
+// Layout: words in groups of kRowWords; byte ((v*G + g)*64 + b)*kRowWords + x
+// (G = ceil(W / kRowWords)) is trial 64*(g*kRowWords + x) + b, so one 16-byte
+// load gives a lane the thresholds of its trial for a whole word group.
+// A wavefront fills 8 nodes x one word group: lane 8j+q draws node j's
+// blocks for trials 8q .. 8q+7 of each word, stages the bytes in LDS and the
+// wavefront writes each node's 1 KB contiguously.
+__device__ __forceinline__ uint32_t kmin_of(uint32_t h, uint32_t wv, uint32_t inv)
+{
+    if (wv == 0) return 255u;
+    // floor(h / wv) from inv = floor(2^32 / wv) (wv >= 2): the estimate is
+    // low by at most one
+    uint32_t q = wv == 1 ? h : __umulhi(h, inv);
+    if (wv != 1 && h - q * wv >= wv) ++q;
+    return q >= 254u ? 255u : q + 1u;
+}
+
 __global__ __launch_bounds__(kBlock) void ltg_kmin_kernel(SimParams P, uint8_t* __restrict__ kmin)
 {
+    __shared__ uint8_t stage[kWaves][8 * 64 * kRowWords];
     const uint64_t n = (uint64_t)P.n;
-    const uint64_t W = P.W;
-    const uint64_t items = ((n + 7) / 8) * W;
+    const uint32_t W = P.W;
+    const uint64_t G = (W + kRowWords - 1) / kRowWords;
+    const uint64_t items = ((n + 7) / 8) * G;
     const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t j = lane >> 3, q = lane & 7u;
+    uint8_t* S = stage[threadIdx.x >> 6];
     for (uint64_t it = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) >> 6; it < items; it += ((uint64_t)gridDim.x * kBlock) >> 6) {
-        const uint32_t w = (uint32_t)(it % W);
-        const uint64_t v = (it / W) * 8 + (lane >> 3);
-        const uint32_t g = lane & 7;
-        if (v >= n) continue;
-        const uint32_t wv = P.node_w[v];
-        const Block4 b = philox_block(v, (uint64_t)w * 8 + g, P.seed, kDomainLtNode);
-        uint32_t packed[2] = {0, 0};
+        const uint64_t grp = it % G;
+        const uint64_t v0 = (it / G) * 8;
+        const uint64_t v = v0 + j;
+        const uint32_t wv = v < n ? P.node_w[v] : 0u;
+        const uint32_t inv = wv >= 2 ? (uint32_t)(0x100000000ull / wv) : 0u;
+        for (uint32_t x = 0; x < kRowWords; ++x) {
+            const uint32_t w = (uint32_t)grp * kRowWords + x;
+            uint32_t k[8];
+            if (v < n && w < W) {
+                const Block4 b = philox_block(v, (uint64_t)w * 8 + q, P.seed, kDomainLtNode);
 #pragma unroll
-        for (uint32_t i = 0; i < 8; ++i) {
-            const uint32_t h = block_lane(b, i);
-            const uint32_t k = wv == 0 ? 255u : (h / wv >= 254u ? 255u : h / wv + 1u);
-            packed[i >> 2] |= k << (8 * (i & 3));
+                for (uint32_t i = 0; i < 8; ++i) k[i] = kmin_of(block_lane(b, i), wv, inv);
+            } else {
+#pragma unroll
+                for (uint32_t i = 0; i < 8; ++i) k[i] = 255u;
+            }
+#pragma unroll
+            for (uint32_t i = 0; i < 8; ++i) S[(j * 64 + 8 * q + i) * kRowWords + x] = (uint8_t)k[i];
         }
-        *reinterpret_cast<uint2*>(kmin + (v * W + w) * 64 + 8 * g) = make_uint2(packed[0], packed[1]);
+        __builtin_amdgcn_wave_barrier();
+        for (uint32_t jj = 0; jj < 8; ++jj) {
+            if (v0 + jj >= n) break;
+            const uint4 val = *reinterpret_cast<const uint4*>(S + (jj * 64 + lane) * kRowWords);
+            *reinterpret_cast<uint4*>(kmin + (((v0 + jj) * G + grp) * 64 + lane) * kRowWords) = val;
+        }
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -789,15 +821,54 @@ __global__ __launch_bounds__(kBlock) void ltg_sweep_kernel(SimParams P, uint32_t
                 WT[lane] = wt;
                 __builtin_amdgcn_wave_barrier();
             }
-            uint32_t wm = wmask;
-            uint32_t kpn0 = 0, kpn1 = 0;
-            if (kMode == 2) {
-                const uint32_t w0 = wg + (uint32_t)__builtin_ctz(wm);
-                for (uint32_t j = 0; j < nn; ++j) {
-                    const uint32_t kv = P.kmin[((uint64_t)(vf + j) * W + w0) * 64 + lane];
-                    if (j < 4) kpn0 |= kv << (8 * j); else kpn1 |= kv << (8 * (j - 4));
+            if (kMode == 2 && !big) {
+                // count thresholds: node by node, all words of the group at
+                // once; a node's 16 thresholds of this lane's trial are one
+                // 16-byte load, fetched one node ahead
+                const uint64_t b0 = __ballot(pn0 != 0), b1 = __ballot(pn1 != 0);
+                uint32_t nodes = 0;
+#pragma unroll
+                for (uint32_t j = 0; j < 8; ++j) nodes |= ((((b0 | b1) >> (8 * j)) & 0xFFull) != 0 ? 1u : 0u) << j;
+                const uint64_t G = (W + kRowWords - 1) / kRowWords;
+                const uint64_t grp = wg / kRowWords;
+                auto kq_of = [&](uint32_t j) -> uint4 {
+                    return *reinterpret_cast<const uint4*>(P.kmin + (((uint64_t)(vf + j) * G + grp) * 64 + lane) * kRowWords);
+                };
+                uint4 kq_next = kq_of((uint32_t)__builtin_ctz(nodes));
+                uint64_t colbits[kRowWords];
+#pragma unroll
+                for (uint32_t x = 0; x < kRowWords; ++x)
+                    colbits[x] = ((wmask >> x) & 1u) ? wave_transpose64(lane < total ? R[lane * kRowPitch + x] : 0ull, lane) : 0ull;
+                while (nodes) {
+                    const uint32_t j = (uint32_t)__builtin_ctz(nodes);
+                    nodes &= nodes - 1;
+                    const uint4 kq = kq_next;
+                    if (nodes) kq_next = kq_of((uint32_t)__builtin_ctz(nodes));
+                    const uint32_t words = (uint32_t)(((b0 >> (8 * j)) & 0xFFull) | (((b1 >> (8 * j)) & 0xFFull) << 8));
+                    const uint64_t v = (uint64_t)vf + j;
+                    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)pre_lane, (int)j);
+                    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)incl, (int)j);
+                    const uint64_t rng = range_of(lo, hi);
+#pragma unroll
+                    for (uint32_t x = 0; x < kRowWords; ++x) {
+                        if (!((words >> x) & 1u)) continue;
+                        const uint64_t pend = pend_of(j, x);
+                        const uint32_t c = (uint32_t)__popcll(colbits[x] & rng);
+                        const uint32_t kw = x < 4 ? kq.x : x < 8 ? kq.y : x < 12 ? kq.z : kq.w;
+                        const uint32_t kj = (kw >> (8 * (x & 3))) & 0xFFu;
+                        const uint64_t dec = __ballot(((pend >> lane) & 1ull) && c >= kj);
+                        if (dec == 0) continue;
+                        const uint32_t w = wg + x;
+                        if (lane == 0) atomic_or64(&P.Anm[v * W + w], dec);
+                        ++changed;
+                        if (marks_now)
+                            for (int64_t e = P.off[v] + lane; e < P.off[v + 1]; e += 64) P.aux[(uint64_t)P.idx[e] * W + w] = sw + 2;
+                    }
                 }
+                __builtin_amdgcn_wave_barrier();
+                continue;
             }
+            uint32_t wm = wmask;
             while (wm) {
                 const uint32_t wl = (uint32_t)__builtin_ctz(wm);
                 wm &= wm - 1;
@@ -809,18 +880,6 @@ __global__ __launch_bounds__(kBlock) void ltg_sweep_kernel(SimParams P, uint32_t
                 if (P.lt_uniform && !big)
                     colbits = wave_transpose64(lane < total ? R[lane * kRowPitch + wl] : 0ull, lane);
                 constexpr bool kTable = kMode == 1;
-                // count thresholds of the next word's nodes (two packed
-                // registers) are fetched while this word is evaluated
-                uint32_t kpack0 = kpn0, kpack1 = kpn1;
-                if (kMode == 2 && wm) {
-                    const uint32_t wn2 = wg + (uint32_t)__builtin_ctz(wm);
-                    kpn0 = 0;
-                    kpn1 = 0;
-                    for (uint32_t j = 0; j < nn; ++j) {
-                        const uint32_t kv = P.kmin[((uint64_t)(vf + j) * W + wn2) * 64 + lane];
-                        if (j < 4) kpn0 |= kv << (8 * j); else kpn1 |= kv << (8 * (j - 4));
-                    }
-                }
                 // nodes one at a time; with the threshold table the next node's
                 // threshold is fetched while the current one is summed
                 auto th_of = [&](uint32_t j) -> uint32_t {
@@ -839,10 +898,8 @@ __global__ __launch_bounds__(kBlock) void ltg_sweep_kernel(SimParams P, uint32_t
                     if (!big) {
                         const uint32_t* base = R32 + 2 * wl + half;
                         if (P.lt_uniform) {
-                            if (kMode != 2) {
-                                const uint32_t c = (uint32_t)__popcll(colbits & range_of(lo, hi));
-                                acc = (uint64_t)c * (uint32_t)__builtin_amdgcn_readlane((int)wn_lane, (int)j);
-                            }
+                            const uint32_t c = (uint32_t)__popcll(colbits & range_of(lo, hi));
+                            acc = (uint64_t)c * (uint32_t)__builtin_amdgcn_readlane((int)wn_lane, (int)j);
                         } else {
                             for (uint32_t i = lo; i < hi; ++i)
                                 acc += (uint32_t)__builtin_amdgcn_sbfe((int)base[2 * kRowPitch * i], bitpos, 1) & WT[i];
@@ -872,19 +929,12 @@ __global__ __launch_bounds__(kBlock) void ltg_sweep_kernel(SimParams P, uint32_t
                         }
                     }
                     // this lane's trial: join when the in-weight exceeds its hash
-                    bool join;
-                    if (kMode == 2 && !big) {
-                        const uint32_t kj = ((j < 4 ? kpack0 : kpack1) >> (8 * (j & 3))) & 0xFFu;
-                        const uint32_t c = (uint32_t)__popcll(colbits & range_of(lo, hi));
-                        join = c >= kj;
-                    } else {
-                        uint32_t h = h_tab;
-                        if (kMode != 1) {
-                            const Block4 blk = philox_block(v, (uint64_t)w * 8 + (lane >> 3), P.seed, kDomainLtNode);
-                            h = block_lane(blk, lane & 7);
-                        }
-                        join = acc > (uint64_t)h;
+                    uint32_t h = h_tab;
+                    if (kMode != 1) {
+                        const Block4 blk = philox_block(v, (uint64_t)w * 8 + (lane >> 3), P.seed, kDomainLtNode);
+                        h = block_lane(blk, lane & 7);
                     }
+                    const bool join = acc > (uint64_t)h;
                     const uint64_t dec = __ballot(((pend >> lane) & 1ull) && join);
                     if (dec == 0) continue;
                     if (lane == 0) atomic_or64(&P.Anm[v * W + w], dec);

@@ -95,9 +95,11 @@ def evaluate(S: mpnn.Surrogate, params, data: dict, idx: np.ndarray, batch: int)
 
 
 def train(S: mpnn.Surrogate, data: dict, epochs: int, batch: int, lr: float, seed: int, val_frac: float = 0.05,
-          checkpoint: str | None = None, log=None, time_budget_s: float | None = None) -> dict:
+          checkpoint: str | None = None, log=None, time_budget_s: float | None = None, eps: float = 1e-20) -> dict:
     """Adam on the mean squared error of sigma / n; returns params and history.
-    With `checkpoint`, state is saved after every epoch and resumed from."""
+    With `checkpoint`, state is saved after every epoch and resumed from.
+    The loss is scaled by 1/n^2, so gradients are around 1e-9: Adam's eps must
+    sit far below them or the steps shrink to nothing."""
     dev = torch.device("cuda", torch.cuda.current_device())
     count = data["sigma"].shape[0]
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -131,7 +133,7 @@ def train(S: mpnn.Surrogate, data: dict, epochs: int, batch: int, lr: float, see
             target.copy_(torch.from_numpy(data["sigma"][b].astype(np.float32)), non_blocking=False)
             S.backward(params, target, grads=grads, loss=loss)
             state["step"] += 1
-            mpnn.adam_step(params, grads, m, v, lr, state["step"])
+            mpnn.adam_step(params, grads, m, v, lr, state["step"], eps=eps)
             if nb % 200 == 0:
                 run_loss += loss.item()
             nb += 1
@@ -243,7 +245,8 @@ def main(argv=None) -> int:
     ap.add_argument("--k", type=int, default=50)
     ap.add_argument("--R", type=int, default=10_000)
     ap.add_argument("--judge-seed", type=int, default=999)
-    ap.add_argument("--skip-celf", action="store_true")
+    ap.add_argument("--methods", default="surrogate,degree_ranked,random_ranked,heuristics,celf",
+                    help="selection methods to run (comma-separated)")
     args = ap.parse_args(argv)
     os.makedirs(args.out, exist_ok=True)
     log = lambda *a: print(*a, flush=True)
@@ -272,25 +275,31 @@ def main(argv=None) -> int:
         S = mpnn.Surrogate(g.n, g.offsets, g.indices, wc.astype(np.float32), max_batch=args.batch)
         params = torch.from_numpy(ck["params"]).cuda()
         sel = {}
+        methods = set(args.methods.split(","))
         runs = [("surrogate", net_scorer(S, params, args.batch), 0.1), ("degree_ranked", degree_scorer(deg), None),
                 ("random_ranked", random_scorer(12), None)]
         for name, scorer, tol in runs:
+            if name not in methods:
+                continue
             res = guided_greedy(G, args.k, args.R, rng_seed=5, scorer=scorer, deg=deg, tol=tol)
             res["judge_sigma"] = judge(G, res["seeds"], args.R, args.judge_seed)
             sel[name] = res
             log(f"[select] {name}: judge sigma {res['judge_sigma']:.2f}, {res['seconds']:.1f}s")
-        top = np.argsort(-deg, kind="stable")[:args.k]
-        sel["top_degree"] = {"seeds": [int(v) for v in top], "judge_sigma": judge(G, top, args.R, args.judge_seed)}
-        rnd = np.random.Generator(np.random.PCG64(13)).choice(g.n, args.k, replace=False)
-        sel["random"] = {"seeds": [int(v) for v in rnd], "judge_sigma": judge(G, rnd, args.R, args.judge_seed)}
-        if not args.skip_celf:
+        if "heuristics" in methods:
+            top = np.argsort(-deg, kind="stable")[:args.k]
+            sel["top_degree"] = {"seeds": [int(v) for v in top], "judge_sigma": judge(G, top, args.R, args.judge_seed)}
+            rnd = np.random.Generator(np.random.PCG64(13)).choice(g.n, args.k, replace=False)
+            sel["random"] = {"seeds": [int(v) for v in rnd], "judge_sigma": judge(G, rnd, args.R, args.judge_seed)}
+            log(f"[select] top degree {sel['top_degree']['judge_sigma']:.2f}, random {sel['random']['judge_sigma']:.2f}")
+        if "celf" in methods:
             c = im.celf(G, args.k, args.R, rng_seed=5)
             c["judge_sigma"] = judge(G, c["seeds"], args.R, args.judge_seed)
             sel["celf"] = c
             log(f"[select] celf: judge sigma {c['judge_sigma']:.2f}, {c['seconds']:.1f}s")
         report["select"] = sel
         S.close()
-    path = os.path.join(args.out, f"report_{args.stage}.json")
+    path = os.path.join(args.out, f"report_{args.stage}_{args.methods.replace(',', '_')}.json" if args.stage == "select"
+                        else f"report_{args.stage}.json")
     with open(path, "w") as f:
         json.dump(report, f, indent=1, default=lambda o: o.tolist() if hasattr(o, "tolist") else str(o))
     log(f"[done] {path}")

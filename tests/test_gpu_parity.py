@@ -186,6 +186,17 @@ def test_lt_grid_threshold_paths_and_direction_switch(ims, flags, alpha):
     run_both(ims, "lt", g.n, g.offsets, g.indices, param, seeds, 200, 23, opts=opts)
 
 
+@pytest.mark.parametrize("T", [1025, 1500])
+def test_lt_grid_count_thresholds_over_several_word_groups(ims, T):
+    """Count-threshold table and sweep with more than one group of 16 words,
+    the last one partial (W = 17 and 24)."""
+    g = synth.chung_lu_directed(20000, 2.1, 8.0, seed=33)
+    param = synth.weighted_cascade(g)
+    seeds = synth.top_outdeg_seeds(g, 20)
+    opts = ims.Opts(shape=2, blocks_per_cu=0, alpha=0.0, profile=0, test_flags=0)
+    run_both(ims, "lt", g.n, g.offsets, g.indices, param, seeds, T, 29, opts=opts)
+
+
 @pytest.mark.parametrize("model", ["ic", "lt"])
 def test_sets_equal_single_runs_and_oracle(ims, model):
     """Many seed sets at once (common random numbers) == each set alone."""
