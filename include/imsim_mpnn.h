@@ -8,8 +8,8 @@
  * a network; the one here is this library's design.
  *
  * Network (one graph, a batch of B seed sets, node-major rows r = v * B + b):
- *   x_v      = [s_v, log(1 + outdeg v), log(1 + indeg v), sum over arcs
- *               (v,u) of a_vu, 0 x 12]            (IMS_MPNN_IN = 16 values)
+ *   x_v      = [s_v, log(1 + outdeg v), log(1 + indeg v), log(1 + sum over
+ *               arcs (v,u) of a_vu), 0 x 12]       (IMS_MPNN_IN = 16 values)
  *   h^0 = x;  h^{l+1}_v = ReLU([h^l_v | sum over arcs (u,v) of a_uv h^l_u] W_l + b_l),
  *             l = 0, 1, 2, hidden width 64
  *   yhat_v   = 1 if v in S, else sigmoid(h^3_v . w_o + b_o)

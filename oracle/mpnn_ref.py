@@ -65,14 +65,14 @@ def in_csr(n, offsets, indices, a):
 
 
 def features(n, offsets, indices, a) -> np.ndarray:
-    """Static node features [log(1+outdeg), log(1+indeg), sum of a over out-arcs],
-    rounded to float32 as the library stores them."""
+    """Static node features [log(1+outdeg), log(1+indeg), log(1 + sum of a over
+    out-arcs)], rounded to float32 as the library stores them."""
     offsets = np.asarray(offsets, dtype=np.int64)
     outdeg = np.diff(offsets)
     indeg = np.bincount(np.asarray(indices, dtype=np.int64), minlength=n)
     src = np.repeat(np.arange(n), outdeg)
     asum = np.bincount(src, weights=np.asarray(a, dtype=np.float64), minlength=n)
-    f = np.stack([np.log1p(outdeg.astype(np.float64)), np.log1p(indeg.astype(np.float64)), asum], axis=1)
+    f = np.stack([np.log1p(outdeg.astype(np.float64)), np.log1p(indeg.astype(np.float64)), np.log1p(asum)], axis=1)
     return f.astype(np.float32).astype(np.float64)
 
 

@@ -107,7 +107,7 @@ struct ims_graph {
         void* p = nullptr;
         uint64_t bytes = 0;
     };
-    Buf A, N[3], Q[3], aux, thp, Anm;
+    Buf A, N[3], Q[3], aux, thp, Anm, nmark;
     // sets mode (ims_simulate_sets): per-slot state
     Buf sA, sN, sQ[3], sact, sstamp, ssteps, sets_dev;
     bool sets_zero_dirty = true;  // sN / sstamp / ssteps must start zeroed
@@ -140,6 +140,7 @@ struct ims_graph {
         for (auto& b : N) release(b);
         for (auto& b : Q) release(b);
         release(aux);
+        release(nmark);
         release(thp);
         release(Anm);
         for (Buf* b : {&sA, &sN, &sQ[0], &sQ[1], &sQ[2], &sact, &sstamp, &ssteps, &sets_dev}) release(*b);
@@ -432,6 +433,7 @@ int ims_simulate(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_t
     } else {
         if ((rc = ensure_buf(g, g->aux, cells * 4, true))) return rc;
         if ((rc = ensure_buf(g, g->Anm, cells * 8, false))) return rc;
+        if ((rc = ensure_buf(g, g->nmark, (uint64_t)g->n * 4, false))) return rc;
     }
     // LT grid shape: threshold prefix table when it fits the budget
     const int test_flags = opts ? opts->test_flags : 0;
@@ -498,6 +500,7 @@ int ims_simulate(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_t
     }
     P.qcount = g->d_qcount;
     P.aux = (uint32_t*)g->aux.p;
+    P.nmark = (uint32_t*)g->nmark.p;
     P.seeds = g->d_seeds;
     P.n_seeds = (uint32_t)sv.size();
     P.seed_arcs = seed_pre.back();
@@ -542,6 +545,7 @@ int ims_simulate(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_t
             // node-major state and sweep marks start cleared every run
             if ((rc = fill_async<uint64_t>(P.Anm, cells, 0ull, s))) return rc;
             if ((rc = fill_async<uint32_t>((uint32_t*)g->aux.p, cells, 0u, s))) return rc;
+            if ((rc = fill_async<uint32_t>((uint32_t*)g->nmark.p, (uint64_t)g->n, 0u, s))) return rc;
             if (lt_mode == 1) {
                 P.th32 = (const uint32_t*)g->thp.p;
                 hipLaunchKernelGGL(imsim::ltg_table_kernel, dim3(blocks), dim3(imsim::kBlock), 0, s, P, (uint32_t*)g->thp.p);

@@ -197,7 +197,7 @@ int dense_weight_grad(ims_mpnn* p, int64_t R, const uint16_t* Xs, const uint16_t
     hipLaunchKernelGGL(dense_bwd_weight_kernel<D>, dim3((unsigned)blocks), dim3(kThreads), 0, s, R, rows_per, Xs, Xn, dZ,
                        p->part, stride);
     MP_HIP(hipGetLastError());
-    hipLaunchKernelGGL(sum_partials_kernel, dim3(grid_for(stride, kThreads, INT32_MAX)), dim3(kThreads), 0, s, stride,
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(grid_for(stride, 32, INT32_MAX)), dim3(kThreads), 0, s, stride,
                        blocks, stride, (const float*)p->part, grads);
     MP_HIP(hipGetLastError());
     return IMS_OK;
@@ -251,7 +251,7 @@ int ims_mpnn_create(int64_t n, int64_t m, const int64_t* offsets, const uint32_t
         for (int64_t e = offsets[v]; e < offsets[v + 1]; ++e) sum += arc_weight[e];
         feat[3 * v + 0] = (float)std::log1p((double)(offsets[v + 1] - offsets[v]));
         feat[3 * v + 1] = (float)std::log1p((double)(in_off[v + 1] - in_off[v]));
-        feat[3 * v + 2] = (float)sum;
+        feat[3 * v + 2] = (float)std::log1p(sum);
     }
 
     std::vector<SpmmItem> items[2];
@@ -410,7 +410,7 @@ int ims_mpnn_forward(ims_mpnn* p, const float* params, const uint32_t* set_offse
     hipLaunchKernelGGL(column_partials_kernel, dim3((unsigned)cb), dim3(kThreads), 0, s, p->n, B, Bp, nodes_per,
                        (const float*)yhat, p->part);
     MP_HIP(hipGetLastError());
-    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(kThreads), 0, s, (int64_t)B, cb, (int64_t)B, (const float*)p->part,
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(grid_for(B, 32, INT32_MAX)), dim3(kThreads), 0, s, (int64_t)B, cb, (int64_t)B, (const float*)p->part,
                        p->pred);
     MP_HIP(hipGetLastError());
     MP_HIP(hipMemcpyAsync(pred, p->pred, B * 4ull, hipMemcpyDeviceToDevice, s));
@@ -439,7 +439,7 @@ int ims_mpnn_backward(ims_mpnn* p, const float* params, const float* target, flo
                            (const uint16_t*)t[IMS_MPNN_T_H3], (const float*)t[IMS_MPNN_T_YHAT], (const float*)p->g,
                            params + IMS_MPNN_OFF_WO, t[IMS_MPNN_T_DZ3], p->part);
         MP_HIP(hipGetLastError());
-        hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(kThreads), 0, s, (int64_t)(kHidden + 1), nb,
+        hipLaunchKernelGGL(sum_partials_kernel, dim3(grid_for(kHidden + 1, 32, INT32_MAX)), dim3(kThreads), 0, s, (int64_t)(kHidden + 1), nb,
                            (int64_t)(kHidden + 1), (const float*)p->part, grads + IMS_MPNN_OFF_WO);
         MP_HIP(hipGetLastError());
     }

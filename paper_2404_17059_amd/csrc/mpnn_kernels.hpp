@@ -425,15 +425,25 @@ __global__ void __launch_bounds__(kThreads) dense_bwd_weight_kernel(int64_t R, i
     }
 }
 
-// out[i] = sum over blk of part[blk * stride + i], i < count, fixed order
-__global__ void sum_partials_kernel(int64_t count, int64_t blocks, int64_t stride, const float* __restrict__ part,
-                                    float* __restrict__ out)
+// out[i] = sum over blk of part[blk * stride + i], i < count, in a fixed
+// order: a workgroup takes 32 outputs; its slice s (of 8) sums blocks s, s+8,
+// s+16, ... and the slices are added in order.
+__global__ void __launch_bounds__(kThreads) sum_partials_kernel(int64_t count, int64_t blocks, int64_t stride,
+                                                                const float* __restrict__ part, float* __restrict__ out)
 {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= count) return;
+    __shared__ float red[kThreads / 32][32];
+    const uint32_t c = threadIdx.x & 31u, sl = threadIdx.x >> 5;
+    const int64_t i = (int64_t)blockIdx.x * 32 + c;
     float s = 0.0f;
-    for (int64_t b = 0; b < blocks; ++b) s += part[b * stride + i];
-    out[i] = s;
+    if (i < count)
+        for (int64_t b = sl; b < blocks; b += kThreads / 32) s += part[b * stride + i];
+    red[sl][c] = s;
+    __syncthreads();
+    if (sl == 0 && i < count) {
+        float t = red[0][c];
+        for (uint32_t k = 1; k < kThreads / 32; ++k) t += red[k][c];
+        out[i] = t;
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -87,6 +87,7 @@ struct SimParams {
     uint64_t* Q[3];     // grid IC: queues of (node, word, chunk); word-local: see below
     uint32_t* qcount;   // grid: per-step counters
     uint32_t* aux;      // word-local: per-word scratch (stamps / queue masks)
+    uint32_t* nmark;    // LT grid shape: per node, the largest sweep mark of any of its words
     const uint32_t* seeds;
     uint32_t n_seeds;
     uint64_t seed_arcs;  // out-arcs of the seeds (predicts the first sweep's changes)
@@ -604,6 +605,7 @@ __global__ __launch_bounds__(kBlock) void ltg_seed_kernel(SimParams P, const uin
         const uint32_t s = P.seeds[lo];
         const uint64_t v = P.idx[P.off[s] + (int64_t)(q - seed_arc_pre[lo])];
         for (uint64_t w = 0; w < W; ++w) P.aux[v * W + w] = 1u;
+        P.nmark[v] = 1u;
     }
 }
 
@@ -690,7 +692,8 @@ __global__ __launch_bounds__(kBlock) void ltg_kmin_kernel(SimParams P, uint8_t* 
 // LT sweep `sw` over all words, in place.  Direction switch: a sweep "marks"
 // when the previous sweep changed fewer than `tau` (node, word) pairs: every
 // node that joins then stamps its out-neighbours with sw + 2 in aux (node-
-// major).  A sweep that follows a marking sweep evaluates only nodes stamped
+// major, per word) and in nmark (per node, so a marked sweep can skip a batch
+// after one load).  A sweep that follows a marking sweep evaluates only nodes stamped
 // >= sw + 1 (sweep 0 follows the seed marks); any other sweep evaluates every
 // node with an inactive trial.  A node none of whose in-neighbours changed
 // since its last evaluation cannot change, so both forms reach the same
@@ -699,7 +702,7 @@ __global__ __launch_bounds__(kBlock) void ltg_kmin_kernel(SimParams P, uint8_t* 
 // kMode: 0 = threshold hashes drawn in the kernel, 1 = threshold table,
 // 2 = count-threshold table (equal in-weights; long rows draw hashes).
 template <int kMode>
-__global__ __launch_bounds__(kBlock) void ltg_sweep_kernel(SimParams P, uint32_t sw, uint32_t tau)
+__global__ __launch_bounds__(kBlock, 4) void ltg_sweep_kernel(SimParams P, uint32_t sw, uint32_t tau)
 {
     __shared__ uint64_t rows[kWaves][64 * kRowPitch];
     __shared__ uint32_t wts[kWaves][64];
@@ -732,6 +735,8 @@ __global__ __launch_bounds__(kBlock) void ltg_sweep_kernel(SimParams P, uint32_t
         const uint32_t nn = uniform32(P.bfirst[bi + 1]) - vf;
         const bool own = lane < nn;
         const uint64_t myv = own ? (uint64_t)vf + lane : 0ull;
+        // a marked sweep skips batches none of whose nodes carries a mark
+        if (marked_only && __ballot(own && P.nmark[myv] >= min_mark) == 0) continue;
         const int64_t kb = own ? P.in_off[myv] : 0;
         const uint32_t dg = own ? (uint32_t)(P.in_off[myv + 1] - kb) : 0u;
         uint32_t incl = dg;
@@ -862,7 +867,11 @@ __global__ __launch_bounds__(kBlock) void ltg_sweep_kernel(SimParams P, uint32_t
                         if (lane == 0) atomic_or64(&P.Anm[v * W + w], dec);
                         ++changed;
                         if (marks_now)
-                            for (int64_t e = P.off[v] + lane; e < P.off[v + 1]; e += 64) P.aux[(uint64_t)P.idx[e] * W + w] = sw + 2;
+                            for (int64_t e = P.off[v] + lane; e < P.off[v + 1]; e += 64) {
+                                const uint64_t t = P.idx[e];
+                                P.aux[t * W + w] = sw + 2;
+                                P.nmark[t] = sw + 2;
+                            }
                     }
                 }
                 __builtin_amdgcn_wave_barrier();
@@ -940,7 +949,11 @@ __global__ __launch_bounds__(kBlock) void ltg_sweep_kernel(SimParams P, uint32_t
                     if (lane == 0) atomic_or64(&P.Anm[v * W + w], dec);
                     ++changed;
                     if (marks_now)
-                        for (int64_t e = P.off[v] + lane; e < P.off[v + 1]; e += 64) P.aux[(uint64_t)P.idx[e] * W + w] = sw + 2;
+                        for (int64_t e = P.off[v] + lane; e < P.off[v + 1]; e += 64) {
+                                const uint64_t t = P.idx[e];
+                                P.aux[t * W + w] = sw + 2;
+                                P.nmark[t] = sw + 2;
+                            }
                 }
             }
             __builtin_amdgcn_wave_barrier();

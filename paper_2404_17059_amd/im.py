@@ -54,15 +54,18 @@ def greedy(graph, k: int, R: int, rng_seed: int, candidates=None, chunk: int = 4
 
 
 def celf(graph, k: int, R: int, rng_seed: int, candidates=None, chunk: int = 4096, batch: int = 64,
-         n: int | None = None) -> dict:
+         n: int | None = None, log=None) -> dict:
     """Lazy greedy.  The heap holds (-gain upper bound, node, round evaluated);
-    stale tops are re-evaluated `batch` at a time against the current S."""
+    stale tops are re-evaluated `batch` at a time against the current S.
+    `log` (optional) receives a progress line per pick."""
     t0 = time.perf_counter()
     n = graph.n if n is None else n
     sigma_of = _evaluator(graph, R, rng_seed, chunk)
     cand = sorted(range(n) if candidates is None else {int(c) for c in candidates})
     first = sigma_of([], cand)
     evals = len(cand)
+    if log:
+        log(f"[celf] first pass: {len(cand)} singletons, {time.perf_counter() - t0:.1f}s")
     heap = [(-int(t), v, 0) for t, v in zip(first, cand)]
     heapq.heapify(heap)
     S: list[int] = []
@@ -74,6 +77,9 @@ def celf(graph, k: int, R: int, rng_seed: int, candidates=None, chunk: int = 409
             S.append(v)
             cur_total += -g
             gains.append(-g / R)
+            if log:
+                log(f"[celf] pick {len(S)}: node {v}, sigma {cur_total / R:.2f}, {evals} evaluations, "
+                    f"{time.perf_counter() - t0:.1f}s")
             continue
         stale = []
         while heap and heap[0][2] != len(S) and len(stale) < batch:

@@ -157,7 +157,7 @@ def train(S: mpnn.Surrogate, data: dict, epochs: int, batch: int, lr: float, see
 # selection
 
 def guided_greedy(graph: Graph, k: int, trials: int, rng_seed: int, scorer, pool_deg: int = 512, pool_score: int = 512,
-                  r: int = 8, deg: np.ndarray | None = None, tol: float | None = 0.1) -> dict:
+                  r: int = 8, deg: np.ndarray | None = None, tol: float | None = 0.1, log=None) -> dict:
     """Greedy with a scorer ranking a candidate pool and Monte Carlo on the
     top r.  scorer(S, pool) -> scores, larger first (the network's scores are
     its sigma(S + v) estimates).  The pool is the top `pool_deg` nodes by
@@ -199,6 +199,8 @@ def guided_greedy(graph: Graph, k: int, trials: int, rng_seed: int, scorer, pool
         S.append(best)
         sigma = best_mc / trials
         prev_rank = ranked
+        if log and (len(S) % 10 == 0 or len(S) == k):
+            log(f"[guided] pick {len(S)}: sigma {sigma:.2f}, {time.perf_counter() - t0:.1f}s")
     return {"seeds": S, "sigma": sigma, "mc_sets": mc_sets, "widened": widened, "seconds": time.perf_counter() - t0}
 
 
@@ -230,12 +232,39 @@ def judge(graph: Graph, seeds, trials: int, rng_seed: int) -> float:
 
 # --------------------------------------------------------------------------
 
+def step_bench(g, wc, batch: int, log, steps: int = 10, warmup: int = 3) -> int:
+    """Time training steps (forward, backward, Adam) on `batch` random sets of
+    1-50 nodes with HIP events on the launch stream."""
+    S = mpnn.Surrogate(g.n, g.offsets, g.indices, wc.astype(np.float32), max_batch=batch)
+    params = torch.from_numpy(mpnn.init_params(1)).cuda()
+    m, v = torch.zeros_like(params), torch.zeros_like(params)
+    offs, nodes = sample_sets(g.n, g.outdeg(), batch, seed=3)
+    target = torch.full((batch,), 100.0, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    tf = tb = 0.0
+    for it in range(warmup + steps):
+        ev[0].record()
+        S.forward_packed(params, offs, nodes)
+        ev[1].record()
+        grads = S.backward(params, target)
+        mpnn.adam_step(params, grads, m, v, 1e-3, it + 1, eps=1e-20)
+        ev[2].record()
+        torch.cuda.synchronize()
+        if it >= warmup:
+            tf += ev[0].elapsed_time(ev[1])
+            tb += ev[1].elapsed_time(ev[2])
+    log(json.dumps({"n": g.n, "m": g.m, "batch": batch, "forward_ms": tf / steps, "backward_adam_ms": tb / steps,
+                    "us_per_set": (tf + tb) / steps / batch * 1e3}))
+    S.close()
+    return 0
+
+
 def main(argv=None) -> int:
     import synth
 
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--out", required=True)
-    ap.add_argument("--stage", default="all", choices=["data", "train", "select", "all"])
+    ap.add_argument("--stage", default="all", choices=["data", "train", "select", "all", "step-bench"])
     ap.add_argument("--pairs", type=int, default=100_000)
     ap.add_argument("--data-trials", type=int, default=1000)
     ap.add_argument("--epochs", type=int, default=8)
@@ -245,6 +274,7 @@ def main(argv=None) -> int:
     ap.add_argument("--k", type=int, default=50)
     ap.add_argument("--R", type=int, default=10_000)
     ap.add_argument("--judge-seed", type=int, default=999)
+    ap.add_argument("--celf-batch", type=int, default=8, help="stale heap entries CELF re-evaluates at once")
     ap.add_argument("--methods", default="surrogate,degree_ranked,random_ranked,heuristics,celf",
                     help="selection methods to run (comma-separated)")
     args = ap.parse_args(argv)
@@ -254,6 +284,8 @@ def main(argv=None) -> int:
     g, wc = synth.chung_lu_wc_200k()
     deg = g.outdeg().astype(np.int64)
     G = Graph(g.n, g.offsets, g.indices, "ic", wc)
+    if args.stage == "step-bench":
+        return step_bench(g, wc, args.batch, log)
     data_path = os.path.join(args.out, "pairs.npz")
     ck_path = os.path.join(args.out, "surrogate.npz")
     report = {"graph": {"n": g.n, "m": g.m, "sha256": g.sha256()}}
@@ -281,7 +313,7 @@ def main(argv=None) -> int:
         for name, scorer, tol in runs:
             if name not in methods:
                 continue
-            res = guided_greedy(G, args.k, args.R, rng_seed=5, scorer=scorer, deg=deg, tol=tol)
+            res = guided_greedy(G, args.k, args.R, rng_seed=5, scorer=scorer, deg=deg, tol=tol, log=log)
             res["judge_sigma"] = judge(G, res["seeds"], args.R, args.judge_seed)
             sel[name] = res
             log(f"[select] {name}: judge sigma {res['judge_sigma']:.2f}, {res['seconds']:.1f}s")
@@ -292,7 +324,7 @@ def main(argv=None) -> int:
             sel["random"] = {"seeds": [int(v) for v in rnd], "judge_sigma": judge(G, rnd, args.R, args.judge_seed)}
             log(f"[select] top degree {sel['top_degree']['judge_sigma']:.2f}, random {sel['random']['judge_sigma']:.2f}")
         if "celf" in methods:
-            c = im.celf(G, args.k, args.R, rng_seed=5)
+            c = im.celf(G, args.k, args.R, rng_seed=5, batch=args.celf_batch, log=log)
             c["judge_sigma"] = judge(G, c["seeds"], args.R, args.judge_seed)
             sel["celf"] = c
             log(f"[select] celf: judge sigma {c['judge_sigma']:.2f}, {c['seconds']:.1f}s")
