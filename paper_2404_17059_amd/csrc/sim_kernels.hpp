@@ -557,15 +557,43 @@ __device__ __forceinline__ uint64_t range_of(uint32_t lo, uint32_t hi)
 // L and L ^ s.
 __device__ __forceinline__ uint64_t wave_transpose64(uint64_t x, uint32_t lane)
 {
-    constexpr uint64_t kHi[6] = {0xFFFFFFFF00000000ull, 0xFFFF0000FFFF0000ull, 0xFF00FF00FF00FF00ull,
-                                 0xF0F0F0F0F0F0F0F0ull, 0xCCCCCCCCCCCCCCCCull, 0xAAAAAAAAAAAAAAAAull};
+    // Lanes L (bit s clear) and L ^ s swap blocks: L keeps the bits k with
+    // (k & s) == 0 and takes its partner's such bits shifted up by s; the
+    // partner keeps the (k & s) != 0 bits and takes L's shifted down.  Each
+    // lane sends only the 32 bits its partner needs.  s = 32, 16, 8 move
+    // whole bytes, packed and unpacked with v_perm_b32 (selector bytes 0-3
+    // pick bytes of the second operand, 4-7 of the first).
+    uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+    {
+        const bool up = (lane & 32u) != 0;
+        const uint32_t r = (uint32_t)__shfl_xor((int)(up ? lo : hi), 32);
+        lo = up ? r : lo;
+        hi = up ? hi : r;
+    }
+    {
+        const bool up = (lane & 16u) != 0;
+        const uint32_t r = (uint32_t)__shfl_xor((int)__builtin_amdgcn_perm(hi, lo, up ? 0x05040100u : 0x07060302u), 16);
+        const uint32_t nlo = __builtin_amdgcn_perm(r, lo, up ? 0x03020504u : 0x05040100u);
+        const uint32_t nhi = __builtin_amdgcn_perm(r, hi, up ? 0x03020706u : 0x07060100u);
+        lo = nlo;
+        hi = nhi;
+    }
+    {
+        const bool up = (lane & 8u) != 0;
+        const uint32_t r = (uint32_t)__shfl_xor((int)__builtin_amdgcn_perm(hi, lo, up ? 0x06040200u : 0x07050301u), 8);
+        const uint32_t nlo = __builtin_amdgcn_perm(r, lo, up ? 0x03050104u : 0x05020400u);
+        const uint32_t nhi = __builtin_amdgcn_perm(r, hi, up ? 0x03070106u : 0x07020600u);
+        lo = nlo;
+        hi = nhi;
+    }
+    x = (uint64_t)lo | ((uint64_t)hi << 32);
+    // s = 4, 2, 1: bit blocks, the whole word exchanged
+    constexpr uint64_t kHi[3] = {0xF0F0F0F0F0F0F0F0ull, 0xCCCCCCCCCCCCCCCCull, 0xAAAAAAAAAAAAAAAAull};
 #pragma unroll
-    for (int r = 0; r < 6; ++r) {
-        const uint32_t sft = 32u >> r;
+    for (int r = 0; r < 3; ++r) {
+        const uint32_t sft = 4u >> r;
         const uint64_t m = kHi[r];  // bit positions k with (k & sft) != 0
         const uint64_t y = __shfl_xor(x, (int)sft);
-        // branch-free: upper lanes keep their m-bits and take the partner's
-        // other bits shifted down; lower lanes the mirror image
         const uint64_t upper = 0ull - (uint64_t)((lane & sft) != 0);
         const uint64_t keep = (m & upper) | (~m & ~upper);
         const uint64_t moved = ((y >> sft) & upper) | ((y << sft) & ~upper);
@@ -861,7 +889,7 @@ __global__ __launch_bounds__(kBlock, 4) void ltg_sweep_kernel(SimParams P, uint3
                         const uint32_t c = (uint32_t)__popcll(colbits[x] & rng);
                         const uint32_t kw = x < 4 ? kq.x : x < 8 ? kq.y : x < 12 ? kq.z : kq.w;
                         const uint32_t kj = (kw >> (8 * (x & 3))) & 0xFFu;
-                        const uint64_t dec = __ballot(((pend >> lane) & 1ull) && c >= kj);
+                        const uint64_t dec = __ballot(c >= kj) & pend;
                         if (dec == 0) continue;
                         const uint32_t w = wg + x;
                         if (lane == 0) atomic_or64(&P.Anm[v * W + w], dec);
@@ -944,7 +972,7 @@ __global__ __launch_bounds__(kBlock, 4) void ltg_sweep_kernel(SimParams P, uint3
                         h = block_lane(blk, lane & 7);
                     }
                     const bool join = acc > (uint64_t)h;
-                    const uint64_t dec = __ballot(((pend >> lane) & 1ull) && join);
+                    const uint64_t dec = __ballot(join) & pend;
                     if (dec == 0) continue;
                     if (lane == 0) atomic_or64(&P.Anm[v * W + w], dec);
                     ++changed;
