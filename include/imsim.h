@@ -138,6 +138,25 @@ int ims_simulate_sets(ims_graph* g, const uint32_t* set_offsets, const uint32_t*
                       uint32_t n_trials, uint64_t rng_seed, const ims_opts* opts, uint64_t* totals,
                       uint32_t* node_counts, void* stream);
 
+/* Marginal spreads from a stored state (greedy's sigma(S + v) - sigma(S),
+ * Section 2, "Influence Maximization").  base_bits (device uint64[W * n],
+ * word-major) is the active_bits output of ims_simulate for a seed set S with
+ * the same n_trials and rng_seed.  Each set X is simulated from A_t(S) with
+ * X added: IC continues the cascade over the same live arcs, LT the same
+ * thresholds, so the final set is exactly A_t(S + X) (IC: reachability over
+ * live arcs; LT: least fixpoint above A_t(S) + X, which is A_t(S + X) since
+ * A_t(S) lies below it).  Outputs count new activations only:
+ *   totals       device uint64[n_sets]: sum over trials of |A_t(S + X) \ A_t(S)|,
+ *                so sigma(S + X) = (total(S) + totals[i]) / n_trials.
+ *   node_counts  device uint32[n_sets * n] (optional): trials in which each
+ *                node is active for S + X but not for S.
+ * Other arguments, errors and asynchrony as ims_simulate_sets; base_bits
+ * must stay unchanged until the call's work is done.  Results are exact only
+ * when base_bits comes from the same graph, n_trials and rng_seed. */
+int ims_simulate_sets_from(ims_graph* g, const uint64_t* base_bits, const uint32_t* set_offsets,
+                           const uint32_t* set_nodes, uint32_t n_sets, uint32_t n_trials, uint64_t rng_seed,
+                           const ims_opts* opts, uint64_t* totals, uint32_t* node_counts, void* stream);
+
 /* Batch: several (graph, seeds, trials, rng_seed) runs, IC and LT mixed,
  * executed by one persistent launch that takes (item, 64-trial word) tasks
  * in a scheduled order, captured once in a HIP graph and replayed.  Each

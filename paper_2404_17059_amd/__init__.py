@@ -70,6 +70,7 @@ _sig("ims_batch_autotune", _int, _P, _int, _P, ctypes.POINTER(Tuning))
 _sig("ims_batch_launch", _int, _P, _P)
 _sig("ims_batch_destroy", _int, _P)
 _sig("ims_simulate_sets", _int, _P, _P, _P, _u32, _u32, _u64, ctypes.POINTER(Opts), _P, _P, _P)
+_sig("ims_simulate_sets_from", _int, _P, _P, _P, _P, _u32, _u32, _u64, ctypes.POINTER(Opts), _P, _P, _P)
 _sig("ims_graph_profile", _int, _P, _int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_u32))
 _sig("ims_debug_hash", _int, _u64, _u64, _P, _P, _P, _i64, _P)
 
@@ -249,6 +250,36 @@ def simulate_sets(graph: Graph, sets, n_trials: int, rng_seed: int, want_node_co
     simulate_sets_into(graph, offs, nodes, n_trials, rng_seed, tot, nc, stream, opts)
     totals = tot.cpu().numpy()[:n_sets]
     out = {"totals": totals, "sigma": totals / float(n_trials)}
+    if want_node_counts:
+        out["node_counts"] = nc.cpu().numpy().view(np.uint32)[:n_sets]
+    return out
+
+
+def simulate_sets_from_into(graph: Graph, base_bits, offsets: np.ndarray, nodes: np.ndarray, n_trials: int, rng_seed: int,
+                            totals, node_counts=None, stream=None, opts: Opts | None = None) -> None:
+    """Enqueue marginal simulations of many sets on top of the state
+    base_bits ([W, n] active bits of a run with the same n_trials and
+    rng_seed); totals receive the new activations only."""
+    n_sets = int(offsets.shape[0]) - 1
+    ptr = lambda t: None if t is None else ctypes.c_void_p(t.data_ptr())
+    _check(_lib.ims_simulate_sets_from(graph.handle, ptr(base_bits), _np_ptr(offsets), _np_ptr(nodes) if nodes.size else None,
+                                       n_sets, int(n_trials), int(rng_seed) & ((1 << 64) - 1),
+                                       ctypes.byref(opts) if opts is not None else None, ptr(totals), ptr(node_counts),
+                                       _stream_handle(stream)), "ims_simulate_sets_from")
+
+
+def simulate_sets_from(graph: Graph, base_bits, sets, n_trials: int, rng_seed: int, want_node_counts: bool = False,
+                       stream=None, opts: Opts | None = None) -> dict:
+    """New activations of each set in `sets` added to the seed set whose run
+    produced base_bits (common random numbers); returns host arrays."""
+    torch = _torch()
+    offs, nodes = pack_sets(sets)
+    n_sets = len(sets)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    tot = torch.empty(max(n_sets, 1), dtype=torch.int64, device=dev)
+    nc = torch.empty((max(n_sets, 1), graph.n), dtype=torch.int32, device=dev) if want_node_counts else None
+    simulate_sets_from_into(graph, base_bits, offs, nodes, n_trials, rng_seed, tot, nc, stream, opts)
+    out = {"new_totals": tot.cpu().numpy()[:n_sets]}
     if want_node_counts:
         out["node_counts"] = nc.cpu().numpy().view(np.uint32)[:n_sets]
     return out

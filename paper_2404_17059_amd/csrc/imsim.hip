@@ -501,6 +501,7 @@ int ims_simulate(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_t
     P.qcount = g->d_qcount;
     P.aux = (uint32_t*)g->aux.p;
     P.nmark = (uint32_t*)g->nmark.p;
+    P.base = nullptr;
     P.seeds = g->d_seeds;
     P.n_seeds = (uint32_t)sv.size();
     P.seed_arcs = seed_pre.back();
@@ -625,8 +626,15 @@ int ims_simulate(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_t
     return IMS_OK;
 }
 
-int ims_simulate_sets(ims_graph* g, const uint32_t* set_offsets, const uint32_t* set_nodes, uint32_t n_sets, uint32_t n_trials,
-                      uint64_t rng_seed, const ims_opts* opts, uint64_t* totals, uint32_t* node_counts, void* stream)
+}  // extern "C"
+
+namespace {
+
+// Many seed sets under one trial range (common random numbers); with `base`
+// the sets start from that word-major state and count new activations only.
+int simulate_sets_impl(ims_graph* g, const uint64_t* base, const uint32_t* set_offsets, const uint32_t* set_nodes, uint32_t n_sets,
+                       uint32_t n_trials, uint64_t rng_seed, const ims_opts* opts, uint64_t* totals, uint32_t* node_counts,
+                       void* stream)
 {
     if (!g) return fail(IMS_E_INVALID_ARG, "ims_simulate_sets: NULL graph");
     if (n_trials == 0) return fail(IMS_E_INVALID_ARG, "ims_simulate_sets: n_trials must be >= 1");
@@ -714,6 +722,7 @@ int ims_simulate_sets(ims_graph* g, const uint32_t* set_offsets, const uint32_t*
     P.set_nodes = d_nodes;
     P.n_sets = n_sets;
     P.totals = totals;
+    P.base = base;
     P.set_node_counts = node_counts;
     P.act = (uint32_t*)g->sact.p;
     P.sstamp = (uint32_t*)g->sstamp.p;
@@ -727,6 +736,24 @@ int ims_simulate_sets(ims_graph* g, const uint32_t* set_offsets, const uint32_t*
         hipLaunchKernelGGL((imsim::word_kernel<true, true>), dim3((uint32_t)slots), dim3(imsim::kTaskBlock), 0, s, P, n);
     IMS_HIP(hipGetLastError());
     return IMS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ims_simulate_sets(ims_graph* g, const uint32_t* set_offsets, const uint32_t* set_nodes, uint32_t n_sets, uint32_t n_trials,
+                      uint64_t rng_seed, const ims_opts* opts, uint64_t* totals, uint32_t* node_counts, void* stream)
+{
+    return simulate_sets_impl(g, nullptr, set_offsets, set_nodes, n_sets, n_trials, rng_seed, opts, totals, node_counts, stream);
+}
+
+int ims_simulate_sets_from(ims_graph* g, const uint64_t* base_bits, const uint32_t* set_offsets, const uint32_t* set_nodes,
+                           uint32_t n_sets, uint32_t n_trials, uint64_t rng_seed, const ims_opts* opts, uint64_t* totals,
+                           uint32_t* node_counts, void* stream)
+{
+    if (!base_bits) return fail(IMS_E_INVALID_ARG, "ims_simulate_sets_from: base_bits is NULL");
+    return simulate_sets_impl(g, base_bits, set_offsets, set_nodes, n_sets, n_trials, rng_seed, opts, totals, node_counts, stream);
 }
 
 }  // extern "C"

@@ -88,6 +88,7 @@ struct SimParams {
     uint32_t* qcount;   // grid: per-step counters
     uint32_t* aux;      // word-local: per-word scratch (stamps / queue masks)
     uint32_t* nmark;    // LT grid shape: per node, the largest sweep mark of any of its words
+    const uint64_t* base;  // sets form: word-major state [W][n] the sets start from, or null
     const uint32_t* seeds;
     uint32_t n_seeds;
     uint64_t seed_arcs;  // out-arcs of the seeds (predicts the first sweep's changes)
@@ -159,14 +160,6 @@ __device__ __forceinline__ uint32_t uniform32(uint32_t x)
 __device__ __forceinline__ uint64_t uniform64(uint64_t x)
 {
     return (uint64_t)uniform32((uint32_t)x) | ((uint64_t)uniform32((uint32_t)(x >> 32)) << 32);
-}
-
-__device__ __forceinline__ uint64_t select8(const uint64_t x[8], uint32_t j)
-{
-    uint64_t r = x[0];
-#pragma unroll
-    for (uint32_t q = 1; q < 8; ++q) r = (j == q) ? x[q] : r;
-    return r;
 }
 
 // Add node J's staged arcs of chunk [c, c+64) to acc[J]: lane t adds the
@@ -309,8 +302,9 @@ __device__ __forceinline__ void lt_decide(const SimParams& P, uint32_t w, uint32
 // consumed.  Each chunk is written to the wavefront's LDS slots, then every
 // lane walks it adding the weight of each arc whose source is active in its
 // trial.
-__device__ __forceinline__ void lt_eval8_core(const SimParams& P, uint64_t* Aw, uint32_t w, uint32_t lane, uint64_t myv,
-                                              uint64_t pl, int64_t kb, uint32_t dg, uint64_t joined[8], ArcStage* stage)
+__device__ __forceinline__ void lt_eval8_core(const SimParams& P, uint64_t* Aw, const uint64_t* Bw, uint32_t w, uint32_t lane,
+                                              uint64_t myv, uint64_t pl, int64_t kb, uint32_t dg, uint64_t joined[8],
+                                              ArcStage* stage)
 {
     const uint64_t n = (uint64_t)P.n;
     if (lane >= 8) {
@@ -374,8 +368,8 @@ __device__ __forceinline__ void lt_eval8_core(const SimParams& P, uint64_t* Aw, 
             const uint64_t k1 = arc_index(q1);
             const uint32_t s0 = q0 < total ? P.in_src32[k0] : 0u;
             const uint32_t s1 = q1 < total ? P.in_src32[k1] : 0u;
-            const uint64_t a0 = q0 < total ? load_relaxed(&Aw[s0]) : 0ull;
-            const uint64_t a1 = q1 < total ? load_relaxed(&Aw[s1]) : 0ull;
+            const uint64_t a0 = q0 < total ? load_relaxed(&Aw[s0]) | (Bw ? Bw[s0] : 0ull) : 0ull;
+            const uint64_t a1 = q1 < total ? load_relaxed(&Aw[s1]) | (Bw ? Bw[s1] : 0ull) : 0ull;
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
                 const uint32_t c = c0 + 64 * q;
@@ -405,8 +399,9 @@ __device__ __forceinline__ void lt_eval8_core(const SimParams& P, uint64_t* Aw, 
             const uint64_t k1 = arc_index(c0 + 64 + lane);
             const uint64_t arc0 = c0 + lane < total ? P.in_arc[k0] : 0ull;
             const uint64_t arc1 = c0 + 64 + lane < total ? P.in_arc[k1] : 0ull;
-            const uint64_t a0 = c0 + lane < total ? load_relaxed(&Aw[(uint32_t)arc0]) : 0ull;
-            const uint64_t a1 = c0 + 64 + lane < total ? load_relaxed(&Aw[(uint32_t)arc1]) : 0ull;
+            const uint64_t a0 = c0 + lane < total ? load_relaxed(&Aw[(uint32_t)arc0]) | (Bw ? Bw[(uint32_t)arc0] : 0ull) : 0ull;
+            const uint64_t a1 =
+                c0 + 64 + lane < total ? load_relaxed(&Aw[(uint32_t)arc1]) | (Bw ? Bw[(uint32_t)arc1] : 0ull) : 0ull;
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
                 const uint32_t c = c0 + 64 * q;
@@ -440,21 +435,27 @@ __device__ __forceinline__ void lt_eval8_core(const SimParams& P, uint64_t* Aw, 
     }
 }
 
-// LT evaluation of nodes vs[0..7] (ids >= n are absent) of word w against
-// the word's state row Aw.  first[j] is set when node j had no active trial
+// LT evaluation of up to 8 nodes of word w against the word's state row Aw,
+// over the read-only base row Bw when given (a node is active in a trial when
+// either has the bit; joins go to Aw only).  Lane j < 8 passes node j in
+// `myv` (ids >= n are absent; other lanes pass anything).  On return ids[j]
+// is node j, joined[j] its new trials, first[j] set when it had no bit in Aw
 // before and joined now.
-__device__ __forceinline__ void lt_eval8(const SimParams& P, uint64_t* Aw, uint32_t w, const uint64_t vs[8], uint32_t lane,
-                                         uint64_t joined[8], bool first[8], ArcStage* stage)
+__device__ __forceinline__ void lt_eval8(const SimParams& P, uint64_t* Aw, const uint64_t* Bw, uint32_t w, uint64_t myv,
+                                         uint32_t lane, uint64_t ids[8], uint64_t joined[8], bool first[8], ArcStage* stage)
 {
     const uint64_t n = (uint64_t)P.n;
     const uint64_t vm = valid_mask(w, P.W, P.T);
-    const uint64_t myv = lane < 8 ? select8(vs, lane) : ~0ull;
+    if (lane >= 8) myv = ~0ull;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) ids[j] = uniform64(__shfl(myv, j));
     const bool okv = myv < n;
-    const uint64_t pl = okv ? (vm & ~load_relaxed(&Aw[myv])) : 0ull;
+    const uint64_t av = okv ? load_relaxed(&Aw[myv]) : 0ull;
+    const uint64_t pl = okv ? (vm & ~(av | (Bw ? Bw[myv] : 0ull))) : 0ull;
     const int64_t kb = pl ? P.in_off[myv] : 0;
     const uint32_t dg = pl ? (uint32_t)(P.in_off[myv + 1] - kb) : 0u;
-    lt_eval8_core(P, Aw, w, lane, myv, pl, kb, dg, joined, stage);
-    const uint64_t was_empty = __ballot(okv && pl == vm);
+    lt_eval8_core(P, Aw, Bw, w, lane, myv, pl, kb, dg, joined, stage);
+    const uint64_t was_empty = __ballot(okv && av == 0);
 #pragma unroll
     for (int j = 0; j < 8; ++j) first[j] = joined[j] != 0 && ((was_empty >> j) & 1ull);
 }
@@ -1034,6 +1035,7 @@ struct TaskShared {
 struct TaskCtx {
     uint32_t w;
     uint64_t* Aw;          // active masks of the task's word
+    const uint64_t* Bw;    // incremental sets form: the word's base masks (read only), else null
     uint64_t* Nw;          // IC: next-step masks (zero between steps)
     uint32_t* L[2];        // frontier node lists
     uint64_t* M[2];        // IC: frontier masks
@@ -1062,12 +1064,14 @@ __device__ __forceinline__ uint32_t ic_task(const SimParams& P, const TaskCtx& c
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < c.n_seeds; i += kTaskBlock) {
         const uint32_t sd = c.seeds[i];
-        c.Aw[sd] = vm;
+        const uint64_t nb = vm & ~(c.Bw ? c.Bw[sd] : 0ull);  // trials the seed newly activates
+        if (nb == 0) continue;
+        c.Aw[sd] = nb;
         if (c.act) c.act[atomicAdd(&sh.act, 1u)] = sd;
         if (P.off[sd + 1] > P.off[sd]) {
             const uint32_t pos = atomicAdd(&sh.cnt[0], 1u);
             c.L[0][pos] = sd;
-            c.M[0][pos] = vm;
+            c.M[0][pos] = nb;
         }
     }
     __syncthreads();
@@ -1099,7 +1103,7 @@ __device__ __forceinline__ uint32_t ic_task(const SimParams& P, const TaskCtx& c
                 const uint32_t v = P.idx[e];
                 const uint32_t th = P.thr[e];
                 if (th == 0) continue;
-                const uint64_t todo = mask & ~c.Aw[v];
+                const uint64_t todo = mask & ~(c.Aw[v] | (c.Bw ? c.Bw[v] : 0ull));
                 if (todo == 0) continue;
                 const uint64_t live = ic_live(todo, th, (uint64_t)e, w, P.seed);
                 if (live == 0) continue;
@@ -1145,7 +1149,9 @@ __device__ __forceinline__ uint32_t lt_task(const SimParams& P, const TaskCtx& c
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < c.n_seeds; i += kTaskBlock) {
         const uint32_t sd = c.seeds[i];
-        c.Aw[sd] = vm;
+        const uint64_t nb = vm & ~(c.Bw ? c.Bw[sd] : 0ull);  // trials the seed newly activates
+        if (nb == 0) continue;
+        c.Aw[sd] = nb;
         c.L[0][atomicAdd(&sh.cnt[0], 1u)] = sd;
         if (c.act) c.act[atomicAdd(&sh.act, 1u)] = sd;
     }
@@ -1178,7 +1184,7 @@ __device__ __forceinline__ uint32_t lt_task(const SimParams& P, const TaskCtx& c
             const int64_t e1 = P.off[u + 1];
             for (int64_t e = P.off[u] + lane; e < e1; e += 64) {
                 const uint32_t v = P.idx[e];
-                if ((vm & ~c.Aw[v]) == 0) continue;
+                if ((vm & ~(c.Aw[v] | (c.Bw ? c.Bw[v] : 0ull))) == 0) continue;
                 if (atomicMax(&c.stamp[v], mark) < mark) c.C[atomicAdd(&sh.cand, 1u)] = v;
             }
         }
@@ -1194,9 +1200,8 @@ __device__ __forceinline__ uint32_t lt_task(const SimParams& P, const TaskCtx& c
             if (it >= ncand) break;
             uint64_t vs[8], joined[8];
             bool first[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) vs[j] = it + j < ncand ? (uint64_t)c.C[it + j] : ~0ull;
-            lt_eval8(P, c.Aw, w, vs, lane, joined, first, sh.stage[threadIdx.x >> 6]);
+            const uint64_t mine = (lane < 8 && it + lane < ncand) ? (uint64_t)c.C[it + lane] : ~0ull;
+            lt_eval8(P, c.Aw, c.Bw, w, mine, lane, vs, joined, first, sh.stage[threadIdx.x >> 6]);
 #pragma unroll
             for (int j = 0; j < 8; ++j)
                 if (joined[j] && lane == 0) {
@@ -1255,7 +1260,7 @@ __device__ __forceinline__ void finish_slot_task(const TaskCtx& c, uint32_t n_ac
 
 // Single-set and many-sets forms.
 template <bool kSets, bool kLT>
-__global__ __launch_bounds__(kTaskBlock) void word_kernel(SimParams P, uint64_t list_cap)
+__global__ __launch_bounds__(kTaskBlock, 2) void word_kernel(SimParams P, uint64_t list_cap)
 {
     __shared__ TaskShared sh;
     const uint64_t n = (uint64_t)P.n;
@@ -1287,6 +1292,7 @@ __global__ __launch_bounds__(kTaskBlock) void word_kernel(SimParams P, uint64_t 
             c.act = nullptr;
         }
         c.Aw = P.A + slot * n;
+        c.Bw = (kSets && P.base) ? P.base + (uint64_t)c.w * n : nullptr;
         c.L[0] = (uint32_t*)P.Q[0] + slot * list_cap;
         c.L[1] = (uint32_t*)P.Q[1] + slot * list_cap;
         if (!kLT) {
@@ -1335,7 +1341,7 @@ struct BatchItem {
 
 // Batch form: tasks[t] = item << 12 | word, in the order the schedule chose.
 // Slot state rows are sized for the largest item.
-__global__ __launch_bounds__(kTaskBlock) void batch_kernel(const BatchItem* __restrict__ items, const uint32_t* __restrict__ tasks,
+__global__ __launch_bounds__(kTaskBlock, 2) void batch_kernel(const BatchItem* __restrict__ items, const uint32_t* __restrict__ tasks,
                                                        uint32_t n_tasks, uint32_t* task_counter, uint64_t max_n,
                                                        uint64_t* sA, uint64_t* sN, uint32_t* sQ0, uint32_t* sQ1, uint64_t* sQ2,
                                                        uint32_t* sact, uint32_t* sstamp, uint32_t* slot_steps, uint32_t* status)
@@ -1359,6 +1365,7 @@ __global__ __launch_bounds__(kTaskBlock) void batch_kernel(const BatchItem* __re
         c.n_seeds = P.n_seeds;
         c.act = sact + slot * max_n;
         c.Aw = sA + slot * max_n;
+        c.Bw = nullptr;
         c.L[0] = sQ0 + slot * max_n;
         c.L[1] = sQ1 + slot * max_n;
         c.Nw = sN + slot * max_n;

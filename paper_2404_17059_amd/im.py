@@ -14,7 +14,7 @@ import time
 
 import numpy as np
 
-from . import Graph, simulate_sets
+from . import Graph, simulate, simulate_sets, simulate_sets_from
 
 
 def _sigma_of(graph: Graph, base: list[int], extra: list[int], R: int, rng_seed: int, chunk: int) -> np.ndarray:
@@ -27,18 +27,48 @@ def _sigma_of(graph: Graph, base: list[int], extra: list[int], R: int, rng_seed:
     return out
 
 
-def _evaluator(graph, R: int, rng_seed: int, chunk: int):
+class _Incremental:
+    """sigma(S + v) from the stored state of S: one full run of S (active
+    bits kept on the device) per change of S, then only the cascades that the
+    added nodes start (exact, see ims_simulate_sets_from)."""
+
+    def __init__(self, graph: Graph, R: int, rng_seed: int, chunk: int):
+        self.graph, self.R, self.rng_seed, self.chunk = graph, R, rng_seed, chunk
+        self.key = None
+        self.bits = None
+        self.total = 0
+
+    def __call__(self, base: list[int], extra: list[int]) -> np.ndarray:
+        if not base:
+            return _sigma_of(self.graph, base, extra, self.R, self.rng_seed, self.chunk)
+        key = tuple(sorted(set(base)))
+        if key != self.key:
+            r = simulate(self.graph, np.array(key, dtype=np.uint32), self.R, self.rng_seed, want_bits=True,
+                         want_node_counts=False)
+            self.bits, self.total, self.key = r["active_bits"], int(r["total"]), key
+        out = np.zeros(len(extra), dtype=np.int64)
+        for i in range(0, len(extra), self.chunk):
+            sets = [np.array([v], dtype=np.uint32) for v in extra[i:i + self.chunk]]
+            out[i:i + self.chunk] = self.total + simulate_sets_from(self.graph, self.bits, sets, self.R,
+                                                                    self.rng_seed)["new_totals"]
+        return out
+
+
+def _evaluator(graph, R: int, rng_seed: int, chunk: int, incremental: bool = False):
     """graph: a Graph (Monte Carlo on the GPU) or a callable
     (base, extra) -> totals standing in for it."""
     if callable(graph) and not isinstance(graph, Graph):
         return graph
+    if incremental:
+        return _Incremental(graph, R, rng_seed, chunk)
     return lambda base, extra: _sigma_of(graph, base, extra, R, rng_seed, chunk)
 
 
-def greedy(graph, k: int, R: int, rng_seed: int, candidates=None, chunk: int = 4096, n: int | None = None) -> dict:
+def greedy(graph, k: int, R: int, rng_seed: int, candidates=None, chunk: int = 4096, n: int | None = None,
+           incremental: bool = False) -> dict:
     """Plain greedy: every round evaluates sigma(S + v) for every candidate."""
     n = graph.n if n is None else n
-    sigma_of = _evaluator(graph, R, rng_seed, chunk)
+    sigma_of = _evaluator(graph, R, rng_seed, chunk, incremental)
     cand = list(range(n)) if candidates is None else [int(c) for c in candidates]
     S: list[int] = []
     cur = 0
@@ -54,13 +84,14 @@ def greedy(graph, k: int, R: int, rng_seed: int, candidates=None, chunk: int = 4
 
 
 def celf(graph, k: int, R: int, rng_seed: int, candidates=None, chunk: int = 4096, batch: int = 64,
-         n: int | None = None, log=None) -> dict:
+         n: int | None = None, log=None, incremental: bool = False) -> dict:
     """Lazy greedy.  The heap holds (-gain upper bound, node, round evaluated);
     stale tops are re-evaluated `batch` at a time against the current S.
+    `incremental` evaluates them from the stored state of S (same values).
     `log` (optional) receives a progress line per pick."""
     t0 = time.perf_counter()
     n = graph.n if n is None else n
-    sigma_of = _evaluator(graph, R, rng_seed, chunk)
+    sigma_of = _evaluator(graph, R, rng_seed, chunk, incremental)
     cand = sorted(range(n) if candidates is None else {int(c) for c in candidates})
     first = sigma_of([], cand)
     evals = len(cand)

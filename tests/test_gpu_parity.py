@@ -221,6 +221,50 @@ def test_sets_equal_single_runs_and_oracle(ims, model):
     G.close()
 
 
+@pytest.mark.parametrize("model,shape", [("ic", 0), ("lt", 0), ("lt", 2)])
+def test_sets_from_stored_state_equal_full_sets(ims, model, shape):
+    """Marginal runs from the active bits of S: new activations of S + X equal
+    sigma(S + X) - sigma(S) of full runs, per set and per node, and the oracle
+    agrees on one set."""
+    g = synth.barabasi_albert(3000, 3, seed=22)
+    param = synth.weighted_cascade(g)
+    rng = np.random.default_rng(12)
+    S = rng.choice(g.n, size=6, replace=False).astype(np.uint32)
+    T, rs = 200, 41
+    say(f"[parity] sets_from model={model} shape={shape} T={T}")
+    G = ims.Graph(g.n, g.offsets, g.indices, model, param)
+    base = ims.simulate(G, S, T, rs, want_bits=True, opts=ims.Opts(shape=shape, blocks_per_cu=0, alpha=0.0, profile=0))
+    extra = [rng.choice(g.n, size=int(rng.integers(1, 5)), replace=True).astype(np.uint32) for _ in range(40)]
+    extra[0] = np.array([], np.uint32)             # nothing added
+    extra[1] = S[:2].copy()                        # already seeds
+    extra[2] = np.array([7, 7, 7], np.uint32)      # duplicates
+    inc = ims.simulate_sets_from(G, base["active_bits"], extra, T, rs, want_node_counts=True)
+    full = ims.simulate_sets(G, [np.concatenate([S, x]) for x in extra], T, rs, want_node_counts=True)
+    np.testing.assert_array_equal(inc["new_totals"], full["totals"] - base["total"])
+    nc_base = base["node_counts"].cpu().numpy().view(np.uint32).astype(np.int64)
+    np.testing.assert_array_equal(inc["node_counts"].astype(np.int64), full["node_counts"].astype(np.int64) - nc_base[None, :])
+    assert inc["new_totals"][0] == 0 and inc["new_totals"][1] == 0
+    enc = oracle.encode(model, param)
+    o_s = oracle.simulate(model, g.n, g.offsets, g.indices, enc, S, T, rs, want_bits=False, want_node_counts=False, threads=8)
+    o_x = oracle.simulate(model, g.n, g.offsets, g.indices, enc, np.concatenate([S, extra[5]]), T, rs, want_bits=False,
+                          want_node_counts=False, threads=8)
+    assert inc["new_totals"][5] == o_x["total"] - o_s["total"]
+    with pytest.raises(ims.ImsError) as e:
+        ims.simulate_sets_from(G, base["active_bits"], [np.array([g.n], np.uint32)], T, rs)
+    assert e.value.code == -4
+
+
+def test_incremental_celf_equals_full_celf(ims):
+    from paper_2404_17059_amd import im
+    g = synth.barabasi_albert(2000, 3, seed=23)
+    param = synth.weighted_cascade(g)
+    for model in ("ic", "lt"):
+        G = ims.Graph(g.n, g.offsets, g.indices, model, param)
+        a = im.celf(G, 5, 300, 13, batch=8, incremental=True)
+        b = im.celf(G, 5, 300, 13, batch=8, incremental=False)
+        assert a["seeds"] == b["seeds"] and a["sigma"] == b["sigma"], model
+
+
 def test_celf_equals_greedy_and_oracle_greedy(ims):
     """CELF on sigma with common random numbers returns exactly the plain
     greedy picks (submodular coverage), and the plain greedy equals a greedy
