@@ -70,6 +70,7 @@ _sig("ims_batch_autotune", _int, _P, _int, _P, ctypes.POINTER(Tuning))
 _sig("ims_batch_launch", _int, _P, _P)
 _sig("ims_batch_destroy", _int, _P)
 _sig("ims_simulate_sets", _int, _P, _P, _P, _u32, _u32, _u64, ctypes.POINTER(Opts), _P, _P, _P)
+_sig("ims_simulate_levels", _int, _P, _P, _u32, _u32, _u64, _u32, _P, _P, _P, _P)
 _sig("ims_simulate_sets_from", _int, _P, _P, _P, _P, _u32, _u32, _u64, ctypes.POINTER(Opts), _P, _P, _P)
 _sig("ims_graph_profile", _int, _P, _int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_u32))
 _sig("ims_debug_hash", _int, _u64, _u64, _P, _P, _P, _i64, _P)
@@ -212,6 +213,31 @@ def simulate(graph: Graph, seeds, n_trials: int, rng_seed: int, want_bits: bool 
     total = int(tot.item())
     return {"trial_counts": tc, "total": total, "mean": total / T, "node_counts": nc,
             "active_bits": bits, "steps": steps}
+
+
+def simulate_levels(graph: Graph, seeds, n_trials: int, rng_seed: int, max_levels: int = 256, stream=None) -> dict:
+    """IC: per-trial counts of nodes first activated at each level
+    (level 0 = seeds); returns host arrays level_counts [levels, T] (trimmed
+    to the levels reached), trial_counts, and the mean spread."""
+    torch = _torch()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    seeds = np.ascontiguousarray(seeds, dtype=np.uint32)
+    T = int(n_trials)
+    lc = torch.empty((int(max_levels), T), dtype=torch.int32, device=dev)
+    tc = torch.empty(T, dtype=torch.int32, device=dev)
+    tot = torch.empty(1, dtype=torch.int64, device=dev)
+    _check(_lib.ims_simulate_levels(graph.handle, _np_ptr(seeds) if seeds.size else None, seeds.shape[0], T,
+                                    int(rng_seed) & ((1 << 64) - 1), int(max_levels), ctypes.c_void_p(lc.data_ptr()),
+                                    ctypes.c_void_p(tc.data_ptr()), ctypes.c_void_p(tot.data_ptr()),
+                                    _stream_handle(stream)), "ims_simulate_levels")
+    steps, guard = graph.last_status(stream)
+    if guard:
+        raise ImsError(-7, "ims_simulate_levels")
+    counts = lc.cpu().numpy().view(np.uint32)
+    used = min(int(max_levels), steps + 1)
+    total = int(tot.item())
+    return {"level_counts": counts[:used], "levels_processed": steps, "truncated": steps + 1 > int(max_levels),
+            "trial_counts": tc.cpu().numpy().view(np.uint32), "total": total, "mean": total / T}
 
 
 def pack_sets(sets) -> tuple[np.ndarray, np.ndarray]:

@@ -383,9 +383,15 @@ int ims_graph_info(const ims_graph* g, int64_t* n, int64_t* m, int* model)
     return IMS_OK;
 }
 
-int ims_simulate(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_t n_trials, uint64_t rng_seed,
-                 const ims_opts* opts, uint32_t* trial_counts, uint32_t* node_counts, uint64_t* total,
-                 uint64_t* active_bits, void* stream)
+}  // extern "C"
+
+namespace {
+
+// One simulation; with level_counts the word-local IC shape also counts the
+// nodes first activated at every level of every trial.
+int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_t n_trials, uint64_t rng_seed,
+                  const ims_opts* opts, uint32_t* trial_counts, uint32_t* node_counts, uint64_t* total, uint64_t* active_bits,
+                  void* stream, uint32_t* level_counts, uint32_t max_levels)
 {
     if (!g) return fail(IMS_E_INVALID_ARG, "ims_simulate: NULL graph");
     if (n_trials == 0) return fail(IMS_E_INVALID_ARG, "ims_simulate: n_trials must be >= 1");
@@ -410,6 +416,7 @@ int ims_simulate(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_t
     // device or the graph is small; grid-wide steps otherwise
     int shape = opts ? opts->shape : 0;
     if (shape == 0) shape = (W >= (uint32_t)g->cus / 4 || n <= 65536) ? 1 : 2;
+    if (level_counts) shape = 1;  // levels are the word-local IC steps
     if (shape != 1 && shape != 2) return fail(IMS_E_INVALID_ARG, "ims_simulate: unknown shape %d", shape);
 
     if (!active_bits && (rc = ensure_buf(g, g->A, cells * 8, false))) return rc;
@@ -502,6 +509,8 @@ int ims_simulate(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_t
     P.aux = (uint32_t*)g->aux.p;
     P.nmark = (uint32_t*)g->nmark.p;
     P.base = nullptr;
+    P.level_counts = level_counts;
+    P.max_levels = max_levels;
     P.seeds = g->d_seeds;
     P.n_seeds = (uint32_t)sv.size();
     P.seed_arcs = seed_pre.back();
@@ -624,6 +633,33 @@ int ims_simulate(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_t
         IMS_HIP(hipGetLastError());
     }
     return IMS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ims_simulate(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_t n_trials, uint64_t rng_seed,
+                 const ims_opts* opts, uint32_t* trial_counts, uint32_t* node_counts, uint64_t* total,
+                 uint64_t* active_bits, void* stream)
+{
+    return simulate_impl(g, seeds, n_seeds, n_trials, rng_seed, opts, trial_counts, node_counts, total, active_bits, stream,
+                         nullptr, 0);
+}
+
+int ims_simulate_levels(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_t n_trials, uint64_t rng_seed,
+                        uint32_t max_levels, uint32_t* level_counts, uint32_t* trial_counts, uint64_t* total, void* stream)
+{
+    if (!g) return fail(IMS_E_INVALID_ARG, "ims_simulate_levels: NULL graph");
+    if (g->model != IMS_MODEL_IC)
+        return fail(IMS_E_UNSUPPORTED, "ims_simulate_levels: IC only (LT here runs in-place sweeps, not synchronous levels)");
+    if (!level_counts || max_levels == 0) return fail(IMS_E_INVALID_ARG, "ims_simulate_levels: level_counts and max_levels >= 1 required");
+    if (n_trials > 0 && (uint64_t)max_levels * n_trials > 0xFFFFFFFFull)
+        return fail(IMS_E_UNSUPPORTED, "ims_simulate_levels: max_levels * n_trials above 2^32");
+    int rc = fill_async<uint32_t>(level_counts, (uint64_t)max_levels * n_trials, 0u, (hipStream_t)stream);
+    if (rc) return rc;
+    return simulate_impl(g, seeds, n_seeds, n_trials, rng_seed, nullptr, trial_counts, nullptr, total, nullptr, stream,
+                         level_counts, max_levels);
 }
 
 }  // extern "C"

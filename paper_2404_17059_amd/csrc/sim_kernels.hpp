@@ -89,6 +89,8 @@ struct SimParams {
     uint32_t* aux;      // word-local: per-word scratch (stamps / queue masks)
     uint32_t* nmark;    // LT grid shape: per node, the largest sweep mark of any of its words
     const uint64_t* base;  // sets form: word-major state [W][n] the sets start from, or null
+    uint32_t* level_counts;  // word-local IC: [max_levels][T] nodes first active at each level, or null
+    uint32_t max_levels;
     const uint32_t* seeds;
     uint32_t n_seeds;
     uint64_t seed_arcs;  // out-arcs of the seeds (predicts the first sweep's changes)
@@ -1028,6 +1030,7 @@ struct TaskShared {
     uint32_t task;
     unsigned long long total;
     uint32_t trial[64];
+    uint32_t lvl[64];  // per-level counts of the task's 64 trials (level counting runs)
     ArcStage stage[kTaskWaves][64];
 };
 
@@ -1047,6 +1050,26 @@ struct TaskCtx {
     uint32_t n_seeds;
 };
 
+// Level counting: every trial bit of `fresh` adds one to its trial's counter.
+__device__ __forceinline__ void count_level_bits(TaskShared& sh, uint64_t fresh)
+{
+    while (fresh) {
+        atomicAdd(&sh.lvl[__builtin_ctzll(fresh)], 1u);
+        fresh &= fresh - 1;
+    }
+}
+
+// Writes the counters of `level` for word w and clears them (threads < 64;
+// the caller separates this from the counting with barriers).
+__device__ __forceinline__ void flush_level(const SimParams& P, TaskShared& sh, uint32_t w, uint32_t level)
+{
+    if (threadIdx.x < 64) {
+        const uint32_t t = 64 * w + threadIdx.x;
+        if (level < P.max_levels && t < P.T) P.level_counts[(uint64_t)level * P.T + t] = sh.lvl[threadIdx.x];
+        sh.lvl[threadIdx.x] = 0;
+    }
+}
+
 // IC cascade of one task.  Per step every wavefront takes frontier entries
 // and walks their out-arcs lane-strided; a node's first new bit of the step
 // appends it to the next list (counter in LDS); after a barrier the next
@@ -1056,17 +1079,20 @@ __device__ __forceinline__ uint32_t ic_task(const SimParams& P, const TaskCtx& c
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t w = c.w;
     const uint64_t vm = valid_mask(w, P.W, P.T);
+    const bool levels = P.level_counts != nullptr;
     if (threadIdx.x == 0) {
         sh.cnt[0] = 0;
         sh.cnt[1] = 0;
         sh.act = 0;
     }
+    if (levels && threadIdx.x < 64) sh.lvl[threadIdx.x] = 0;
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < c.n_seeds; i += kTaskBlock) {
         const uint32_t sd = c.seeds[i];
         const uint64_t nb = vm & ~(c.Bw ? c.Bw[sd] : 0ull);  // trials the seed newly activates
         if (nb == 0) continue;
         c.Aw[sd] = nb;
+        if (levels) count_level_bits(sh, nb);
         if (c.act) c.act[atomicAdd(&sh.act, 1u)] = sd;
         if (P.off[sd + 1] > P.off[sd]) {
             const uint32_t pos = atomicAdd(&sh.cnt[0], 1u);
@@ -1075,6 +1101,10 @@ __device__ __forceinline__ uint32_t ic_task(const SimParams& P, const TaskCtx& c
         }
     }
     __syncthreads();
+    if (levels) {
+        flush_level(P, sh, w, 0);
+        __syncthreads();
+    }
     uint32_t cur = 0, steps = 0;
     for (;;) {
         const uint32_t cnt = sh.cnt[cur];
@@ -1109,6 +1139,7 @@ __device__ __forceinline__ uint32_t ic_task(const SimParams& P, const TaskCtx& c
                 if (live == 0) continue;
                 const uint64_t old = atomic_or64(&c.Aw[v], live);
                 const uint64_t fresh = live & ~old;
+                if (levels) count_level_bits(sh, fresh);
                 if (c.act && old == 0) c.act[atomicAdd(&sh.act, 1u)] = v;
                 if (fresh == 0 || P.off[v + 1] == P.off[v]) continue;
                 if (atomic_or64(&c.Nw[v], fresh) == 0) {
@@ -1118,6 +1149,7 @@ __device__ __forceinline__ uint32_t ic_task(const SimParams& P, const TaskCtx& c
             }
         }
         __syncthreads();
+        if (levels) flush_level(P, sh, w, steps);
         const uint32_t nc = sh.cnt[nxt];
         for (uint32_t i = threadIdx.x; i < nc; i += kTaskBlock) {
             const uint32_t v = (nxt ? c.L[1] : c.L[0])[i];

@@ -48,6 +48,20 @@ def numpy_hash32_table(rng_seed: int, domain: int, n_trials: int, n_ids: int) ->
     return out
 
 
+def bfs_distance(n: int, src: np.ndarray, dst: np.ndarray, seeds) -> np.ndarray:
+    """Arcs on a shortest path from `seeds` to each node over arcs src->dst
+    (-1 when unreachable), by scipy's unweighted shortest paths from an extra
+    super-source."""
+    seeds = np.unique(np.asarray(seeds, dtype=np.int64))
+    if seeds.size == 0:
+        return np.full(n, -1, dtype=np.int64)
+    s = np.concatenate([np.asarray(src, dtype=np.int64), np.full(seeds.size, n)])
+    d = np.concatenate([np.asarray(dst, dtype=np.int64), seeds])
+    mat = sp.csr_matrix((np.ones(s.size, dtype=np.float64), (s, d)), shape=(n + 1, n + 1))
+    dist = csg.shortest_path(mat, directed=True, unweighted=True, indices=n)[:n]
+    return np.where(np.isinf(dist), -1, dist - 1).astype(np.int64)
+
+
 def reachable(n: int, src: np.ndarray, dst: np.ndarray, seeds) -> np.ndarray:
     """Boolean mask of nodes reachable from `seeds` over arcs src->dst,
     by scipy's breadth-first search on a graph with one extra super-source."""

@@ -221,6 +221,50 @@ def test_sets_equal_single_runs_and_oracle(ims, model):
     G.close()
 
 
+@pytest.mark.parametrize("case", ["random", "er_ic_1k"])
+def test_ic_level_counts_match_oracle_levels(ims, case):
+    """Per-trial counts of nodes first active at each level equal the
+    histogram of the oracle's activation levels."""
+    if case == "random":
+        rng = np.random.default_rng(31)
+        n = 700
+        src = rng.integers(0, n, size=2500)
+        dst = rng.integers(0, n, size=2500)
+        off, idx = pins.csr_from_arcs(n, src, dst)
+        param = rng.choice([0.0, 0.2, 0.5, 1.0], size=idx.shape[0])
+        seeds, T, rs = np.array([1, 2, 3, 400], np.uint32), 333, 55
+    else:
+        w = synth.er_ic_1k()
+        n, off, idx, param, seeds, T, rs = w.graph.n, w.graph.offsets, w.graph.indices, w.param, w.seeds, w.n_trials, w.rng_seed
+    say(f"[parity] levels case={case} n={n} T={T}")
+    G = ims.Graph(n, off, idx, "ic", param)
+    got = ims.simulate_levels(G, seeds, T, rs, max_levels=512)
+    assert not got["truncated"]
+    enc = oracle.encode("ic", param)
+    r = oracle.simulate("ic", n, off, idx, enc, seeds, T, rs, want_levels=True, threads=8)
+    L = got["level_counts"].shape[0]
+    expect = np.zeros((max(L, int(r["levels"].max()) + 1), T), dtype=np.int64)
+    for t in range(T):
+        lv = r["levels"][t]
+        expect[:, t] = np.bincount(lv[lv >= 0], minlength=expect.shape[0])
+    np.testing.assert_array_equal(got["level_counts"].astype(np.int64), expect[:L])
+    assert expect[L:].sum() == 0
+    np.testing.assert_array_equal(got["level_counts"].sum(axis=0), got["trial_counts"])
+    assert got["total"] == int(np.asarray(r["trial_counts"]).sum())
+    # a short buffer keeps the first levels and reports the truncation
+    short = ims.simulate_levels(G, seeds, T, rs, max_levels=3)
+    np.testing.assert_array_equal(short["level_counts"], got["level_counts"][:3])
+    assert short["truncated"] == (got["levels_processed"] + 1 > 3)
+
+
+def test_level_counts_reject_lt(ims):
+    g = synth.barabasi_albert(500, 3, seed=24)
+    G = ims.Graph(g.n, g.offsets, g.indices, "lt", synth.weighted_cascade(g))
+    with pytest.raises(ims.ImsError) as e:
+        ims.simulate_levels(G, np.array([1], np.uint32), 64, 1)
+    assert e.value.code == -8
+
+
 @pytest.mark.parametrize("model,shape", [("ic", 0), ("lt", 0), ("lt", 2)])
 def test_sets_from_stored_state_equal_full_sets(ims, model, shape):
     """Marginal runs from the active bits of S: new activations of S + X equal

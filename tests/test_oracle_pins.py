@@ -121,6 +121,26 @@ def test_ic_sets_equal_live_arc_reachability(gseed):
 
 
 @pytest.mark.parametrize("gseed", [0, 1])
+def test_ic_levels_equal_live_arc_bfs_distance(gseed):
+    """A node's activation level is its shortest live-arc distance from the
+    seed set (the synchronous step of Section 2 at which it activates)."""
+    rng = np.random.default_rng(20 + gseed)
+    n = 40
+    src, dst = random_digraph(n, 160, rng, self_loops=True)
+    off, idx = pins.csr_from_arcs(n, src, dst)
+    m = idx.shape[0]
+    thr = oracle.encode_p(rng.choice([0.0, 0.1, 0.4, 0.8, 1.0], size=m))
+    seeds = np.array([5, 11, 5], dtype=np.uint32)
+    T, rs = 100, 300 + gseed
+    r = oracle.simulate("ic", n, off, idx, thr, seeds, T, rs, want_levels=True)
+    coins = pins.numpy_hash32_table(rs, 1, T, m)
+    arc_src = np.repeat(np.arange(n), np.diff(off))
+    for t in range(T):
+        live = (thr == 0xFFFFFFFF) | (coins[t] < thr)
+        np.testing.assert_array_equal(r["levels"][t], pins.bfs_distance(n, arc_src[live], idx[live], seeds))
+
+
+@pytest.mark.parametrize("gseed", [0, 1])
 def test_lt_sets_equal_least_fixpoint(gseed):
     rng = np.random.default_rng(10 + gseed)
     n = 24
