@@ -31,6 +31,16 @@ WORKLOADS = {
     "ba_ic_100k": "ba_ic_100k",
     "er_ic_1k": "er_ic_1k",
 }
+# IC benchmark graphs after the paper's Section 4 (ER / Watts-Strogatz / a
+# Barabasi-Albert stand-in for the Facebook graph x TV / UR / WC weights)
+SUITE = ["er_tv", "er_ur", "er_wc", "ws_tv", "ws_ur", "ws_wc", "ba_fb_tv", "ba_fb_ur", "ba_fb_wc"]
+
+
+def load_workload(name: str):
+    import synth
+    if name in WORKLOADS:
+        return getattr(synth, WORKLOADS[name])()
+    return synth.paper_ic_suite()[SUITE.index(name[len("paper_"):])]
 KERNEL_SOURCES = ["paper_2404_17059_amd/csrc/sim_kernels.hpp", "paper_2404_17059_amd/csrc/philox.hpp"]
 
 
@@ -97,12 +107,56 @@ def copy_calibration(mib: int) -> int:
     return 0
 
 
+def run_suite(args) -> int:
+    """The nine IC benchmark workloads, each timed as in the main mode; one
+    JSON line with the summed work over the summed time and the per-workload
+    figures."""
+    import torch
+
+    import paper_2404_17059_amd as ims
+    import synth
+
+    rows, tot_exams, tot_s, tot_trials = [], 0, 0.0, 0
+    for w in synth.paper_ic_suite():
+        g = w.graph
+        G = ims.Graph(g.n, g.offsets, g.indices, w.model, w.param)
+        T = w.n_trials
+        dev = torch.device("cuda", 0)
+        tc = torch.empty(T, dtype=torch.int32, device=dev)
+        tot = torch.empty(1, dtype=torch.int64, device=dev)
+        nc = torch.empty(g.n, dtype=torch.int32, device=dev)
+        for _ in range(args.warmup):
+            ims.simulate_into(G, w.seeds, T, w.rng_seed, tc, tot, nc)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ims.simulate_into(G, w.seeds, T, w.rng_seed, tc, tot, nc)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        counts = nc.cpu().numpy().view(np.uint32).astype(np.int64)
+        exams = int((counts * g.outdeg()).sum())
+        rows.append({"workload": w.name, "n": g.n, "m": g.m, "ms": round(dt * 1e3, 4), "mean_spread": int(tot.item()) / T,
+                     "exams_per_s": exams / dt, "trials_per_s": T / dt})
+        tot_exams += exams
+        tot_s += dt
+        tot_trials += T
+        log(f"[bench] {w.name}: {dt * 1e3:.3f} ms per {T} trials, mean spread {int(tot.item()) / T:.1f}")
+        G.close()
+    print(json.dumps({"metric": METRIC, "value": tot_exams / tot_s, "unit": "edge-examinations/s", "n_gpus": 1,
+                      "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(tot_s * 1e3, 4),
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+                      "data": "synthetic", "config": {"workload": "ic_paper_suite_9x1000_trials_100_seeds"},
+                      "trials_per_sec": tot_trials / tot_s, "suite": rows}), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="lt_chunglu_1m", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="lt_chunglu_1m",
+                    choices=sorted(WORKLOADS) + ["paper_" + x for x in SUITE] + ["paper_suite"])
     ap.add_argument("--cpu-sample", type=int, default=64, help="oracle trials timed for cpu_baseline (0 = skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB three times (HBM counter calibration)")
@@ -117,12 +171,13 @@ def main() -> int:
     import torch
 
     import paper_2404_17059_amd as ims
-    import synth
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.workload == "paper_suite":
+        return run_suite(args)
     t0 = time.perf_counter()
-    w = getattr(synth, WORKLOADS[args.workload])()
+    w = load_workload(args.workload)
     g = w.graph
     log(f"[bench] workload {w.name}: n={g.n} m={g.m} T={w.n_trials} seeds={len(w.seeds)} "
         f"generated in {time.perf_counter() - t0:.1f}s")

@@ -88,6 +88,20 @@ def erdos_renyi_directed(n: int, avg_out_degree: float, seed: int) -> Graph:
     return from_arcs(n, src, dst)
 
 
+def erdos_renyi_undirected(n: int, p: float, seed: int) -> Graph:
+    """Undirected G(n, p): each of the n(n-1)/2 pairs is an edge with
+    probability p (edge count Binomial, pairs drawn without repetition);
+    both arc directions kept."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pairs = n * (n - 1) // 2
+    k = int(rng.binomial(pairs, p))
+    idx = np.sort(rng.choice(pairs, size=k, replace=False))
+    # pair index -> (a, b), a < b, row-major over the upper triangle
+    a = (n - 2 - np.floor(np.sqrt(-8.0 * idx + 4.0 * n * (n - 1) - 7) / 2.0 - 0.5)).astype(np.int64)
+    b = (idx + a + 1 - n * (n - 1) // 2 + (n - a) * ((n - a) - 1) // 2).astype(np.int64)
+    return from_arcs(n, np.concatenate([a, b]), np.concatenate([b, a]))
+
+
 def barabasi_albert(n: int, m_attach: int, seed: int) -> Graph:
     """Barabasi-Albert preferential attachment, both arc directions kept.
 
@@ -290,6 +304,26 @@ def er_ic_1k(n_trials: int = 1000) -> Workload:
     g = erdos_renyi_directed(1000, 10.0, seed=101)
     return Workload("ic_er_n1000_d10_p0.1_s10", "ic", g, uniform_p(g, 0.1),
                     random_seeds(g.n, 10, seed=201), n_trials, 1)
+
+
+def paper_ic_suite(n_trials: int = 1000) -> list[Workload]:
+    """IC benchmark workloads after Section 4 ("Benchmarks"): 100 random
+    seeds, 1,000 trials, undirected edges as two arcs, on an Erdos-Renyi graph
+    (n = 2,000, p = 0.002), a Watts-Strogatz graph (n = 10,000, k = 10,
+    p = 0.007) and, standing in for the SNAP Facebook graph (4,039 nodes,
+    88,234 edges, not available here), a Barabasi-Albert graph with 4,039
+    nodes and m = 22; each with trivalency (TV), uniformly random (UR) and
+    weighted-cascade (WC) arc probabilities."""
+    graphs = [("er", erdos_renyi_undirected(2000, 0.002, seed=104)),
+              ("ws", watts_strogatz(10000, 10, 0.007, seed=107)),
+              ("ba_fb", barabasi_albert(4039, 22, seed=108))]
+    out = []
+    for gi, (gname, g) in enumerate(graphs):
+        params = {"tv": trivalency(g, seed=300 + gi), "ur": uniform_random(g, seed=310 + gi), "wc": weighted_cascade(g)}
+        seeds = random_seeds(g.n, 100, seed=320 + gi)
+        for ename, par in params.items():
+            out.append(Workload(f"ic_{gname}_{ename}_n{g.n}_s100", "ic", g, par, seeds, n_trials, 20 + gi))
+    return out
 
 
 def ba_ic_100k(n_trials: int = 10000, n: int = 100_000) -> Workload:

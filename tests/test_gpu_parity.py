@@ -3,6 +3,8 @@ oracle: every trial's final active set, per-trial counts, per-node counts and
 the total must be identical."""
 import sys
 
+import functools
+
 import numpy as np
 import pytest
 
@@ -219,6 +221,19 @@ def test_sets_equal_single_runs_and_oracle(ims, model):
     again = ims.simulate_sets(G, sets[::-1], T, rs)
     assert (again["totals"] == got["totals"][::-1]).all()
     G.close()
+
+
+@functools.lru_cache(maxsize=1)
+def paper_suite():
+    return synth.paper_ic_suite()
+
+
+@pytest.mark.parametrize("i", range(9))
+def test_paper_benchmark_suite_full_parity(ims, i):
+    """The Section 4 benchmark stand-ins (ER / WS / BA x TV / UR / WC, 100
+    seeds, 1,000 trials): every trial's active set equals the oracle's."""
+    w = paper_suite()[i]
+    run_both(ims, w.model, w.graph.n, w.graph.offsets, w.graph.indices, w.param, w.seeds, w.n_trials, w.rng_seed)
 
 
 @pytest.mark.parametrize("case", ["random", "er_ic_1k"])

@@ -72,3 +72,39 @@ def test_workload_seeds():
     top = synth.top_outdeg_seeds(g, 10)
     d = g.outdeg()
     assert np.all(d[top] >= np.sort(d)[-10])
+
+
+def test_paper_ic_suite():
+    ws = synth.paper_ic_suite()
+    assert [w.name.split("_n")[0] for w in ws] == ["ic_er_tv", "ic_er_ur", "ic_er_wc", "ic_ws_tv", "ic_ws_ur", "ic_ws_wc",
+                                                     "ic_ba_fb_tv", "ic_ba_fb_ur", "ic_ba_fb_wc"]
+    pins = {0: ("5f9b8905d935f4f872c0603b1c2bff7de006f191bd385de07151ea8c3424a443", 8040),
+            3: ("22e811e27c6f2e8c999a9478ee8ea7aa4cb876232c0e3d4fbeb42ff23fa50e04", 100000),
+            6: ("e4e30eda7573108b412019075b431f3b2c6e90e65c923f1d7f3908da2512e337", 176748)}
+    for i, (sha, m) in pins.items():
+        g = ws[i].graph
+        assert g.m == m and g.sha256() == sha and simple(g)
+        src, dst = g.arc_sources(), g.indices.astype(np.int64)
+        fwd = set(zip(src.tolist(), dst.tolist()))
+        assert all((v, u) in fwd for u, v in fwd)       # undirected edges as two arcs
+    for w in ws:
+        assert w.n_trials == 1000 and len(set(w.seeds.tolist())) == 100
+        kind = w.name.split("_")[-3]
+        if kind == "tv":
+            assert set(np.unique(w.param)) <= {0.1, 0.01, 0.001}
+        elif kind == "ur":
+            assert w.param.min() >= 0 and w.param.max() <= 1
+        else:
+            indeg = w.graph.indeg()
+            np.testing.assert_allclose(w.param, 1.0 / indeg[w.graph.indices.astype(np.int64)])
+
+
+def test_undirected_erdos_renyi_pairs():
+    g = synth.erdos_renyi_undirected(60, 0.3, seed=3)
+    assert simple(g)
+    src, dst = g.arc_sources(), g.indices.astype(np.int64)
+    assert np.all(np.bincount(src, minlength=60) == np.bincount(dst, minlength=60))
+    # expected edge count n(n-1)/2 * p within 5 sd
+    e = g.m // 2
+    mu = 60 * 59 / 2 * 0.3
+    assert abs(e - mu) < 5 * np.sqrt(mu * 0.7)
