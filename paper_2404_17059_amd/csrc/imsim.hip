@@ -497,7 +497,7 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
     P.lt_uniform = g->lt_uniform && !(test_flags & 4) ? 1 : 0;
     P.thp = nullptr;
     P.th32 = nullptr;
-    P.kmin = nullptr;
+    P.kplanes = nullptr;
     P.thp_shift = (test_flags & 2) ? 31u : 16u;
     P.A = A;
     P.Anm = (uint64_t*)g->Anm.p;
@@ -563,8 +563,8 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
                 hipLaunchKernelGGL(imsim::ltg_table_kernel, dim3(blocks), dim3(imsim::kBlock), 0, s, P, (uint32_t*)g->thp.p);
                 IMS_HIP(hipGetLastError());
             } else if (lt_mode == 2) {
-                P.kmin = (const uint8_t*)g->thp.p;
-                hipLaunchKernelGGL(imsim::ltg_kmin_kernel, dim3(blocks), dim3(imsim::kBlock), 0, s, P, (uint8_t*)g->thp.p);
+                P.kplanes = (const uint64_t*)g->thp.p;
+                hipLaunchKernelGGL(imsim::ltg_kmin_kernel, dim3(blocks), dim3(imsim::kBlock), 0, s, P, (uint64_t*)g->thp.p);
                 IMS_HIP(hipGetLastError());
             }
             const uint64_t work = std::max<uint64_t>(seed_pre.back(), (uint64_t)P.n_seeds * W);

@@ -73,9 +73,11 @@ struct SimParams {
     // LT grid shape: every threshold hash, node-major [n][W][64] (or null)
     const uint32_t* __restrict__ th32;
     // LT grid shape, equal in-weights: per (node, trial) the least number of
-    // active in-arc pieces that makes the node join, floor(h / w_v) + 1,
-    // saturated at 255; node-major [n][W][64] (or null)
-    const uint8_t* __restrict__ kmin;
+    // active in-arc pieces that makes the node join, k = floor(h / w_v) + 1,
+    // saturated at 127, stored as complemented bit planes: uint64
+    // ((v*G + g)*16 + x)*8 + b (G = ceil(W / 16)) holds NOT bit b of k for the
+    // 64 trials of word 16g + x (plane 7 is all ones) (or null)
+    const uint64_t* __restrict__ kplanes;
     // LT grid shape: node batches whose in-arcs fit one 64-arc chunk (or one
     // node with more); batch b holds nodes bfirst[b] .. bfirst[b+1]-1
     const uint32_t* __restrict__ bfirst;
@@ -663,24 +665,29 @@ __global__ __launch_bounds__(kBlock) void ltg_table_kernel(SimParams P, uint32_t
 
 // Count-threshold table (equal in-weights).  With c active in-arc pieces of
 // weight w_v, c * w_v > h exactly when c >= floor(h / w_v) + 1, so the table
-// holds k = min(255, floor(H(seed, LT, t, v) / w_v) + 1) per (node, trial).
-// Layout: words in groups of kRowWords; byte ((v*G + g)*64 + b)*kRowWords + x
-// (G = ceil(W / kRowWords)) is trial 64*(g*kRowWords + x) + b, so one 16-byte
-// load gives a lane the thresholds of its trial for a whole word group.
+// holds k = floor(H(seed, LT, t, v) / w_v) + 1 per (node, trial), saturated at
+// 127 (a node evaluated from staged rows has at most 64 in-arc pieces, so a
+// saturated k is never reached either way).  The sweep compares bit-sliced
+// counts against it, so it is stored as complemented bit planes: for node v,
+// word group g (G = ceil(W / kRowWords) groups) and word x of the group, the
+// uint64 ((v*G + g)*kRowWords + x)*8 + b has bit t = NOT bit b of k for trial
+// 64*(g*kRowWords + x) + t (b < 7; plane 7 is all ones).
 // A wavefront fills 8 nodes x one word group: lane 8j+q draws node j's
-// blocks for trials 8q .. 8q+7 of each word, stages the bytes in LDS and the
-// wavefront writes each node's 1 KB contiguously.
+// blocks for trials 8q .. 8q+7 of each word and stages the bytes in LDS; then,
+// node by node, lane t holds its trial's 16 bytes as two 64-bit rows, and one
+// 64x64 bit transpose per row turns bit b of byte x into lane 8x+b, which is
+// the table's order, so each node's 1 KB is written contiguously.
 __device__ __forceinline__ uint32_t kmin_of(uint32_t h, uint32_t wv, uint32_t inv)
 {
-    if (wv == 0) return 255u;
+    if (wv == 0) return 127u;
     // floor(h / wv) from inv = floor(2^32 / wv) (wv >= 2): the estimate is
     // low by at most one
     uint32_t q = wv == 1 ? h : __umulhi(h, inv);
     if (wv != 1 && h - q * wv >= wv) ++q;
-    return q >= 254u ? 255u : q + 1u;
+    return q >= 126u ? 127u : q + 1u;
 }
 
-__global__ __launch_bounds__(kBlock) void ltg_kmin_kernel(SimParams P, uint8_t* __restrict__ kmin)
+__global__ __launch_bounds__(kBlock) void ltg_kmin_kernel(SimParams P, uint64_t* __restrict__ kplanes)
 {
     __shared__ uint8_t stage[kWaves][8 * 64 * kRowWords];
     const uint64_t n = (uint64_t)P.n;
@@ -705,7 +712,7 @@ __global__ __launch_bounds__(kBlock) void ltg_kmin_kernel(SimParams P, uint8_t* 
                 for (uint32_t i = 0; i < 8; ++i) k[i] = kmin_of(block_lane(b, i), wv, inv);
             } else {
 #pragma unroll
-                for (uint32_t i = 0; i < 8; ++i) k[i] = 255u;
+                for (uint32_t i = 0; i < 8; ++i) k[i] = 127u;
             }
 #pragma unroll
             for (uint32_t i = 0; i < 8; ++i) S[(j * 64 + 8 * q + i) * kRowWords + x] = (uint8_t)k[i];
@@ -714,10 +721,63 @@ __global__ __launch_bounds__(kBlock) void ltg_kmin_kernel(SimParams P, uint8_t* 
         for (uint32_t jj = 0; jj < 8; ++jj) {
             if (v0 + jj >= n) break;
             const uint4 val = *reinterpret_cast<const uint4*>(S + (jj * 64 + lane) * kRowWords);
-            *reinterpret_cast<uint4*>(kmin + (((v0 + jj) * G + grp) * 64 + lane) * kRowWords) = val;
+            const uint64_t r0 = wave_transpose64((uint64_t)val.x | ((uint64_t)val.y << 32), lane);
+            const uint64_t r1 = wave_transpose64((uint64_t)val.z | ((uint64_t)val.w << 32), lane);
+            uint64_t* dst = kplanes + ((v0 + jj) * G + grp) * (kRowWords * 8);
+            dst[lane] = ~r0;
+            dst[64 + lane] = ~r1;
         }
         __builtin_amdgcn_wave_barrier();
     }
+}
+
+// Bit-sliced counting: bit t of c[b] is bit b of trial t's count.  add4 adds
+// four 0/1 vectors with three full adders and a carry ripple from weight 4
+// (counts stay below 128).  v_bitop3_b32 evaluates any function of three
+// bits: truth table 0x96 is their parity, 0xE8 their majority.
+__device__ __forceinline__ uint64_t parity3(uint64_t a, uint64_t b, uint64_t c)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_bitop3_b32((uint32_t)a, (uint32_t)b, (uint32_t)c, 0x96);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_bitop3_b32((uint32_t)(a >> 32), (uint32_t)(b >> 32), (uint32_t)(c >> 32), 0x96);
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+__device__ __forceinline__ uint64_t majority3(uint64_t a, uint64_t b, uint64_t c)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_bitop3_b32((uint32_t)a, (uint32_t)b, (uint32_t)c, 0xE8);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_bitop3_b32((uint32_t)(a >> 32), (uint32_t)(b >> 32), (uint32_t)(c >> 32), 0xE8);
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+__device__ __forceinline__ void full_add(uint64_t a, uint64_t b, uint64_t c, uint64_t& sum, uint64_t& carry)
+{
+    sum = parity3(a, b, c);
+    carry = majority3(a, b, c);
+}
+
+__device__ __forceinline__ void add4(uint64_t (&c)[7], uint64_t x0, uint64_t x1, uint64_t x2, uint64_t x3)
+{
+    uint64_t s0, y1, y2, z;
+    full_add(c[0], x0, x1, s0, y1);
+    full_add(s0, x2, x3, c[0], y2);
+    full_add(c[1], y1, y2, c[1], z);
+#pragma unroll
+    for (int b = 2; b < 7; ++b) {
+        const uint64_t t = c[b] & z;
+        c[b] ^= z;
+        z = t;
+    }
+}
+
+// Trials whose count c is at least k, from the bit planes of c and of the
+// 7-bit complement nk = 127 - k: c + nk + 1 = c - k + 128 carries out of bit
+// 6 exactly when c >= k.
+__device__ __forceinline__ uint64_t count_ge(const uint64_t (&c)[7], const uint64_t (&nk)[8])
+{
+    uint64_t carry = ~0ull;
+#pragma unroll
+    for (int b = 0; b < 7; ++b) carry = majority3(c[b], nk[b], carry);
+    return carry;
 }
 
 // LT sweep `sw` over all words, in place.  Direction switch: a sweep "marks"
@@ -735,7 +795,8 @@ __global__ __launch_bounds__(kBlock) void ltg_kmin_kernel(SimParams P, uint8_t* 
 template <int kMode>
 __global__ __launch_bounds__(kBlock, 4) void ltg_sweep_kernel(SimParams P, uint32_t sw, uint32_t tau)
 {
-    __shared__ uint64_t rows[kWaves][64 * kRowPitch];
+    // 64 staged rows, and 4 more that the count form may read (masked)
+    __shared__ uint64_t rows[kWaves][68 * kRowPitch];
     __shared__ uint32_t wts[kWaves][64];
     if (sw >= 1 && load_relaxed32(&P.qcount[sw - 1]) == 0) return;
     if (sw >= P.cap) {
@@ -792,38 +853,9 @@ __global__ __launch_bounds__(kBlock, 4) void ltg_sweep_kernel(SimParams P, uint3
 
         for (uint32_t wg = 0; wg < P.W; wg += kRowWords) {
             const uint32_t gw = P.W - wg < kRowWords ? P.W - wg : kRowWords;
-            // words of this group with a node to evaluate: lane 8j+x holds the
-            // decidable trials of node j, word wg+x (pn0) and wg+x+8 (pn1)
-            uint64_t pn0 = 0, pn1 = 0;
-            uint32_t wmask = 0;
-#pragma unroll
-            for (uint32_t pass = 0; pass < 2; ++pass) {
-                const uint32_t j = lane >> 3, wl = (lane & 7) + 8 * pass;
-                uint64_t pn = 0;
-                if (j < nn && wl < gw) {
-                    const uint64_t v = (uint64_t)vf + j;
-                    const uint32_t w = wg + wl;
-                    pn = valid_mask(w, P.W, P.T) & ~load_relaxed(&P.Anm[v * W + w]);
-                    if (pn && marked_only && P.aux[v * W + w] < min_mark) pn = 0;
-                }
-                if (pass) pn1 = pn; else pn0 = pn;
-                uint64_t b = __ballot(pn != 0);
-                b |= b >> 32;
-                b |= b >> 16;
-                b |= b >> 8;
-                wmask |= (uint32_t)(b & 0xFFull) << (8 * pass);
-            }
-            wmask = uniform32(wmask);
-            if (wmask == 0) continue;
-            // pending trials of node j at word slot wl (uniform)
-            auto pend_of = [&](uint32_t j, uint32_t wl) -> uint64_t {
-                const uint64_t x = wl >= 8 ? pn1 : pn0;
-                const int src = (int)(8 * j + (wl & 7));
-                return (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, src) |
-                       ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), src) << 32);
-            };
-            if (!big) {
-                // stage the mask rows (this word group) of all in-arc sources
+            // stage the mask rows (this word group) of all in-arc sources:
+            // R[i][x] = state of in-arc i's source at word wg + x
+            auto stage_rows = [&]() {
                 uint32_t src = 0, wt = 0;
                 if (lane < total) {
                     if (P.lt_uniform) {
@@ -856,58 +888,129 @@ __global__ __launch_bounds__(kBlock, 4) void ltg_sweep_kernel(SimParams P, uint3
                 for (uint32_t x = 0; x < kRowWords; ++x) R[lane * kRowPitch + x] = row[x];
                 WT[lane] = wt;
                 __builtin_amdgcn_wave_barrier();
-            }
+            };
             if (kMode == 2 && !big) {
-                // count thresholds: node by node, all words of the group at
-                // once; a node's 16 thresholds of this lane's trial are one
-                // 16-byte load, fetched one node ahead
-                const uint64_t b0 = __ballot(pn0 != 0), b1 = __ballot(pn1 != 0);
-                uint32_t nodes = 0;
+                // count thresholds, bit-sliced: in pass p, lane 16i + x takes
+                // node 4p + i at word wg + x, adds the staged masks of the
+                // node's in-arcs into per-trial counts held as bit planes, and
+                // compares them with the node's threshold planes
+                uint64_t pq[2];
+                uint32_t passes = 0;
 #pragma unroll
-                for (uint32_t j = 0; j < 8; ++j) nodes |= ((((b0 | b1) >> (8 * j)) & 0xFFull) != 0 ? 1u : 0u) << j;
+                for (uint32_t p = 0; p < 2; ++p) {
+                    const uint32_t j = 4 * p + (lane >> 4), x = lane & 15u;
+                    uint64_t pn = 0;
+                    if (j < nn && x < gw) {
+                        const uint64_t v = (uint64_t)vf + j;
+                        const uint32_t w = wg + x;
+                        pn = valid_mask(w, P.W, P.T) & ~load_relaxed(&P.Anm[v * W + w]);
+                        if (pn && marked_only && P.aux[v * W + w] < min_mark) pn = 0;
+                    }
+                    pq[p] = pn;
+                    passes |= (__ballot(pn != 0) != 0 ? 1u : 0u) << p;
+                }
+                passes = uniform32(passes);
+                if (passes == 0) continue;
+                stage_rows();
                 const uint64_t G = (W + kRowWords - 1) / kRowWords;
                 const uint64_t grp = wg / kRowWords;
-                auto kq_of = [&](uint32_t j) -> uint4 {
-                    return *reinterpret_cast<const uint4*>(P.kmin + (((uint64_t)(vf + j) * G + grp) * 64 + lane) * kRowWords);
-                };
-                uint4 kq_next = kq_of((uint32_t)__builtin_ctz(nodes));
-                uint64_t colbits[kRowWords];
 #pragma unroll
-                for (uint32_t x = 0; x < kRowWords; ++x)
-                    colbits[x] = ((wmask >> x) & 1u) ? wave_transpose64(lane < total ? R[lane * kRowPitch + x] : 0ull, lane) : 0ull;
-                while (nodes) {
-                    const uint32_t j = (uint32_t)__builtin_ctz(nodes);
-                    nodes &= nodes - 1;
-                    const uint4 kq = kq_next;
-                    if (nodes) kq_next = kq_of((uint32_t)__builtin_ctz(nodes));
-                    const uint32_t words = (uint32_t)(((b0 >> (8 * j)) & 0xFFull) | (((b1 >> (8 * j)) & 0xFFull) << 8));
+                for (uint32_t p = 0; p < 2; ++p) {
+                    if (!((passes >> p) & 1u)) continue;
+                    const uint32_t x = lane & 15u, j = 4 * p + (lane >> 4);
+                    const uint64_t pend = pq[p];
                     const uint64_t v = (uint64_t)vf + j;
-                    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)pre_lane, (int)j);
-                    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)incl, (int)j);
-                    const uint64_t rng = range_of(lo, hi);
+                    uint64_t k[8];
+                    if (pend) {
+                        const uint4* kp = reinterpret_cast<const uint4*>(P.kplanes + ((v * G + grp) * kRowWords + x) * 8);
 #pragma unroll
-                    for (uint32_t x = 0; x < kRowWords; ++x) {
-                        if (!((words >> x) & 1u)) continue;
-                        const uint64_t pend = pend_of(j, x);
-                        const uint32_t c = (uint32_t)__popcll(colbits[x] & rng);
-                        const uint32_t kw = x < 4 ? kq.x : x < 8 ? kq.y : x < 12 ? kq.z : kq.w;
-                        const uint32_t kj = (kw >> (8 * (x & 3))) & 0xFFu;
-                        const uint64_t dec = __ballot(c >= kj) & pend;
-                        if (dec == 0) continue;
-                        const uint32_t w = wg + x;
-                        if (lane == 0) atomic_or64(&P.Anm[v * W + w], dec);
-                        ++changed;
-                        if (marks_now)
-                            for (int64_t e = P.off[v] + lane; e < P.off[v + 1]; e += 64) {
+                        for (uint32_t q = 0; q < 4; ++q) {
+                            const uint4 t = kp[q];
+                            k[2 * q] = (uint64_t)t.x | ((uint64_t)t.y << 32);
+                            k[2 * q + 1] = (uint64_t)t.z | ((uint64_t)t.w << 32);
+                        }
+                    } else {
+#pragma unroll
+                        for (uint32_t q = 0; q < 8; ++q) k[q] = 0;
+                    }
+                    const uint32_t lo = (uint32_t)__shfl((int)pre_lane, (int)j);
+                    const uint32_t dj = (uint32_t)__shfl((int)dg, (int)j);
+                    const uint32_t d = pend ? dj : 0u;
+                    // rows to add: the longest in-arc row among nodes with work
+                    const uint64_t bp = __ballot(pend != 0);
+                    uint32_t maxd = 0;
+#pragma unroll
+                    for (uint32_t i = 0; i < 4; ++i) {
+                        const uint32_t di = (uint32_t)__builtin_amdgcn_readlane((int)dg, (int)(4 * p + i));
+                        if ((bp >> (16 * i)) & 0xFFFFull) maxd = di > maxd ? di : maxd;
+                    }
+                    uint64_t c[7] = {0, 0, 0, 0, 0, 0, 0};
+                    for (uint32_t r = 0; r < maxd; r += 4) {
+                        // rows lo + r .. lo + r + 3; a lane whose row has
+                        // ended reads rows it masks (at most row 67)
+                        const uint32_t base = lo + r < 64u ? lo + r : 64u;
+                        const uint64_t* rr = R + base * kRowPitch + x;
+                        uint64_t in[4];
+#pragma unroll
+                        for (uint32_t u = 0; u < 4; ++u) in[u] = rr[u * kRowPitch];
+#pragma unroll
+                        for (uint32_t u = 0; u < 4; ++u) in[u] = r + u < d ? in[u] : 0ull;
+                        add4(c, in[0], in[1], in[2], in[3]);
+                    }
+                    const uint64_t dec = count_ge(c, k) & pend;
+                    const uint64_t db = __ballot(dec != 0);
+                    if (db == 0) continue;
+                    if (dec) atomic_or64(&P.Anm[v * W + wg + x], dec);
+                    changed += (uint32_t)__popcll(db);
+                    if (marks_now) {
+                        uint64_t mb = db;
+                        while (mb) {
+                            const uint32_t bit = (uint32_t)__builtin_ctzll(mb);
+                            mb &= mb - 1;
+                            const uint64_t vm = (uint64_t)vf + 4 * p + (bit >> 4);
+                            const uint32_t w = wg + (bit & 15u);
+                            for (int64_t e = P.off[vm] + lane; e < P.off[vm + 1]; e += 64) {
                                 const uint64_t t = P.idx[e];
                                 P.aux[t * W + w] = sw + 2;
                                 P.nmark[t] = sw + 2;
                             }
+                        }
                     }
                 }
                 __builtin_amdgcn_wave_barrier();
                 continue;
             }
+            // words of this group with a node to evaluate: lane 8j+x holds the
+            // decidable trials of node j, word wg+x (pn0) and wg+x+8 (pn1)
+            uint64_t pn0 = 0, pn1 = 0;
+            uint32_t wmask = 0;
+#pragma unroll
+            for (uint32_t pass = 0; pass < 2; ++pass) {
+                const uint32_t j = lane >> 3, wl = (lane & 7) + 8 * pass;
+                uint64_t pn = 0;
+                if (j < nn && wl < gw) {
+                    const uint64_t v = (uint64_t)vf + j;
+                    const uint32_t w = wg + wl;
+                    pn = valid_mask(w, P.W, P.T) & ~load_relaxed(&P.Anm[v * W + w]);
+                    if (pn && marked_only && P.aux[v * W + w] < min_mark) pn = 0;
+                }
+                if (pass) pn1 = pn; else pn0 = pn;
+                uint64_t b = __ballot(pn != 0);
+                b |= b >> 32;
+                b |= b >> 16;
+                b |= b >> 8;
+                wmask |= (uint32_t)(b & 0xFFull) << (8 * pass);
+            }
+            wmask = uniform32(wmask);
+            if (wmask == 0) continue;
+            // pending trials of node j at word slot wl (uniform)
+            auto pend_of = [&](uint32_t j, uint32_t wl) -> uint64_t {
+                const uint64_t x = wl >= 8 ? pn1 : pn0;
+                const int src = (int)(8 * j + (wl & 7));
+                return (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, src) |
+                       ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), src) << 32);
+            };
+            if (!big) stage_rows();
             uint32_t wm = wmask;
             while (wm) {
                 const uint32_t wl = (uint32_t)__builtin_ctz(wm);
