@@ -100,7 +100,11 @@ struct ims_graph {
     uint32_t* d_in_src32 = nullptr;  // source per in-arc (uniform-weight form)
     uint32_t* d_node_w = nullptr;    // common weight piece per node (uniform-weight form)
     bool lt_uniform = false;
+    uint32_t kp_stride = 8;          // planes per (node, word) of the count-threshold table
     uint32_t* d_bfirst = nullptr;    // LT grid shape: first node of each batch
+    uint32_t* d_bdesc = nullptr;     // LT grid shape: 4 words per batch (see SimParams::bdesc)
+    uint32_t* d_bigb = nullptr;      // LT grid shape: batches with more than 64 in-arc pieces
+    uint32_t nbig = 0;
     uint32_t nbatch = 0;
     // workspace: byte buffers that only grow
     struct Buf {
@@ -152,6 +156,8 @@ struct ims_graph {
         dev_free(d_in_src32);
         dev_free(d_node_w);
         dev_free(d_bfirst);
+        dev_free(d_bdesc);
+        dev_free(d_bigb);
         dev_free(d_qcount);
         dev_free(d_seeds);
         dev_free(d_seed_pre);
@@ -321,6 +327,18 @@ int ims_graph_create(int64_t n, int64_t m, const int64_t* offsets, const uint32_
                 else if (piece != node_w[v]) { uniform = false; break; }
             }
         g->lt_uniform = uniform;
+        // count-threshold planes: an even count S with 2^S - 1 above every
+        // count a node with at most 64 in-arc pieces can reach
+        {
+            int64_t dmax = 0;
+            for (int64_t v = 0; v < n; ++v) {
+                const int64_t d = in_off[v + 1] - in_off[v];
+                if (d <= 64 && d > dmax) dmax = d;
+            }
+            uint32_t planes = 2;
+            while (planes < 8 && ((1ll << planes) - 1) <= dmax) planes += 2;
+            g->kp_stride = planes;
+        }
         if (uniform) {
             for (int64_t k = 0; k < mi; ++k) src32[k] = (uint32_t)in_arc[k];
             if ((rc = dev_alloc(&g->d_in_src32, (uint64_t)mi))) return bail(rc);
@@ -354,8 +372,24 @@ int ims_graph_create(int64_t n, int64_t m, const int64_t* offsets, const uint32_
         }
         if (bcnt > 0) bfirst.push_back((uint32_t)n);
         g->nbatch = (uint32_t)(bfirst.size() - 1);
+        std::vector<uint32_t> bdesc((size_t)g->nbatch * 4 + 4, 0), bigb;
+        for (uint32_t b = 0; b < g->nbatch; ++b) {
+            const int64_t a0 = in_off[bfirst[b]], pieces = in_off[bfirst[b + 1]] - a0;
+            if (pieces > 64) bigb.push_back(b);
+            bdesc[4 * b] = bfirst[b];
+            bdesc[4 * b + 1] = (bfirst[b + 1] - bfirst[b]) | ((uint32_t)std::min<int64_t>(pieces, 0xFFFFFF) << 8);
+            bdesc[4 * b + 2] = (uint32_t)a0;
+            bdesc[4 * b + 3] = (uint32_t)((uint64_t)a0 >> 32);
+        }
         if ((rc = dev_alloc(&g->d_bfirst, bfirst.size()))) return bail(rc);
-        if (hipMemcpy(g->d_bfirst, bfirst.data(), sizeof(uint32_t) * bfirst.size(), hipMemcpyHostToDevice) != hipSuccess)
+        if ((rc = dev_alloc(&g->d_bdesc, bdesc.size()))) return bail(rc);
+        g->nbig = (uint32_t)bigb.size();
+        bigb.push_back(0);
+        if ((rc = dev_alloc(&g->d_bigb, bigb.size()))) return bail(rc);
+        if (hipMemcpy(g->d_bigb, bigb.data(), sizeof(uint32_t) * bigb.size(), hipMemcpyHostToDevice) != hipSuccess)
+            return bail(fail(IMS_E_HIP, "batch upload failed"));
+        if (hipMemcpy(g->d_bfirst, bfirst.data(), sizeof(uint32_t) * bfirst.size(), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(g->d_bdesc, bdesc.data(), sizeof(uint32_t) * bdesc.size(), hipMemcpyHostToDevice) != hipSuccess)
             return bail(fail(IMS_E_HIP, "batch upload failed"));
     }
     g->cap = (uint32_t)std::min<int64_t>(n + 8, 0xFFFFFFF0ll);
@@ -446,17 +480,20 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
     }
     // LT grid shape: threshold prefix table when it fits the budget
     const int test_flags = opts ? opts->test_flags : 0;
-    // LT grid shape threshold form: count thresholds (equal in-weights, 64 B
-    // per node-word, words padded to whole groups), full hashes (256 B), or
-    // hashes drawn in the kernel
+    // LT grid shape threshold form: count thresholds (equal in-weights, 8 B
+    // per plane and node-word, words padded to whole groups), full hashes
+    // (256 B), or hashes drawn in the kernel
     int lt_mode = 0;
-    const uint64_t kmin_bytes = (uint64_t)g->n * ((W + imsim::kRowWords - 1) / imsim::kRowWords) * 64ull * imsim::kRowWords;
+    const uint64_t kmin_bytes =
+        (uint64_t)g->n * ((W + imsim::kRowWords - 1) / imsim::kRowWords) * imsim::kRowWords * 8ull * g->kp_stride;
     if (shape == 2 && g->model == IMS_MODEL_LT && !(test_flags & 1)) {
         if (g->lt_uniform && !(test_flags & 4) && kmin_bytes <= kThresholdTableBudget && !(test_flags & 8)) lt_mode = 2;
         else if (cells * 256 <= kThresholdTableBudget) lt_mode = 1;
     }
     const bool use_table = lt_mode != 0;
-    if (use_table && (rc = ensure_buf(g, g->thp, lt_mode == 2 ? kmin_bytes : cells * 256, false))) return rc;
+    // (the count-threshold table has 64 bytes of padding: the sweep reads 64
+    // bytes from each (node, word)'s first plane)
+    if (use_table && (rc = ensure_buf(g, g->thp, lt_mode == 2 ? kmin_bytes + 64 : cells * 256, false))) return rc;
     if (g->seeds_cap < sv.size() || !g->d_seeds) {
         dev_free(g->d_seeds);
         dev_free(g->d_seed_pre);
@@ -498,10 +535,14 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
     P.thp = nullptr;
     P.th32 = nullptr;
     P.kplanes = nullptr;
+    P.kp_stride = g->kp_stride;
     P.thp_shift = (test_flags & 2) ? 31u : 16u;
     P.A = A;
     P.Anm = (uint64_t*)g->Anm.p;
     P.bfirst = g->d_bfirst;
+    P.bdesc = reinterpret_cast<const imsim::u32x4*>(g->d_bdesc);
+    P.bigb = g->d_bigb;
+    P.nbig = g->nbig;
     P.nbatch = g->nbatch;
     for (int i = 0; i < 3; ++i) {
         P.N[i] = (uint64_t*)g->N[i].p;
@@ -584,8 +625,13 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
                     hipLaunchKernelGGL(imsim::grid_ic_level_kernel, dim3(blocks), dim3(imsim::kBlock), 0, s, P, st);
                 else
                 {
-                    if (lt_mode == 2)
+                    if (lt_mode == 2) {
                         hipLaunchKernelGGL(imsim::ltg_sweep_kernel<2>, dim3(blocks), dim3(imsim::kBlock), 0, s, P, st, tau);
+                        if (g->nbig)
+                            hipLaunchKernelGGL(imsim::ltg_sweep_kernel<3>,
+                                               dim3(std::min<uint32_t>(blocks, (g->nbig + imsim::kWaves - 1) / imsim::kWaves)),
+                                               dim3(imsim::kBlock), 0, s, P, st, tau);
+                    }
                     else if (lt_mode == 1)
                         hipLaunchKernelGGL(imsim::ltg_sweep_kernel<1>, dim3(blocks), dim3(imsim::kBlock), 0, s, P, st, tau);
                     else

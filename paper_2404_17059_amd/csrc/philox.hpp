@@ -29,16 +29,29 @@ struct Block4 {
     uint64_t w0, w1, w2, w3;
 };
 
+// Full 128-bit product of two 64-bit words from four 32 x 32 -> 64 partial
+// products: a*b = al*bl + 2^32 (al*bh + ah*bl) + 2^64 ah*bh, with the middle
+// terms accumulated so that no partial sum overflows 64 bits.
+__device__ __forceinline__ void mul_wide(uint64_t a, uint64_t b, uint64_t& lo, uint64_t& hi)
+{
+    const uint32_t al = (uint32_t)a, ah = (uint32_t)(a >> 32);
+    const uint32_t bl = (uint32_t)b, bh = (uint32_t)(b >> 32);
+    const uint64_t p0 = (uint64_t)al * bl;
+    const uint64_t t = (uint64_t)al * bh + (p0 >> 32);
+    const uint64_t u = (uint64_t)ah * bl + (uint32_t)t;
+    hi = (uint64_t)ah * bh + ((t >> 32) + (u >> 32));
+    lo = (u << 32) | (uint32_t)p0;
+}
+
 // Philox4x64-10 of counter (c0, c1, 0, 0) under key (k0, k1).
 __device__ __forceinline__ Block4 philox_block(uint64_t c0, uint64_t c1, uint64_t k0, uint64_t k1)
 {
     uint64_t x0 = c0, x1 = c1, x2 = 0, x3 = 0;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint64_t lo_a = kPhiloxM0 * x0;
-        const uint64_t hi_a = __umul64hi(kPhiloxM0, x0);
-        const uint64_t lo_b = kPhiloxM1 * x2;
-        const uint64_t hi_b = __umul64hi(kPhiloxM1, x2);
+        uint64_t lo_a, hi_a, lo_b, hi_b;
+        mul_wide(kPhiloxM0, x0, lo_a, hi_a);
+        mul_wide(kPhiloxM1, x2, lo_b, hi_b);
         const uint64_t n0 = hi_b ^ x1 ^ k0;
         const uint64_t n2 = hi_a ^ x3 ^ k1;
         x0 = n0;

@@ -48,6 +48,8 @@ constexpr uint32_t kMaxWords = 4096;  // grid-shape queue items carry the word i
 constexpr uint32_t kRowWords = 16;   // LT grid shape: words of a source row staged per pass
 constexpr uint32_t kRowPitch = 17;   // LT grid shape: LDS row pitch in uint64 (odd: spreads banks)
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
 struct SimParams {
     int64_t n;
     uint32_t T;
@@ -74,14 +76,22 @@ struct SimParams {
     const uint32_t* __restrict__ th32;
     // LT grid shape, equal in-weights: per (node, trial) the least number of
     // active in-arc pieces that makes the node join, k = floor(h / w_v) + 1,
-    // saturated at 127, stored as complemented bit planes: uint64
-    // ((v*G + g)*16 + x)*8 + b (G = ceil(W / 16)) holds NOT bit b of k for the
-    // 64 trials of word 16g + x (plane 7 is all ones) (or null)
+    // saturated at 2^S - 1 (at most 127) with S = kp_stride, stored as
+    // complemented bit planes: uint64 ((v*G + g)*16 + x)*S + b
+    // (G = ceil(W / 16)) holds NOT bit b of k for the 64 trials of word
+    // 16g + x (or null)
     const uint64_t* __restrict__ kplanes;
+    uint32_t kp_stride;  // planes per (node, word) in kplanes: 2, 4, 6 or 8
     // LT grid shape: node batches whose in-arcs fit one 64-arc chunk (or one
     // node with more); batch b holds nodes bfirst[b] .. bfirst[b+1]-1
     const uint32_t* __restrict__ bfirst;
     uint32_t nbatch;
+    // per batch: first node, node count | min(in-arc pieces, 2^24 - 1) << 8,
+    // and the in-CSR position of its first piece (two halves)
+    const u32x4* __restrict__ bdesc;
+    // batches of one node with more than 64 in-arc pieces
+    const uint32_t* __restrict__ bigb;
+    uint32_t nbig;
     // state
     uint64_t* A;        // [W][n]
     uint64_t* Anm;      // LT grid shape: [n][W] (node-major)
@@ -666,68 +676,76 @@ __global__ __launch_bounds__(kBlock) void ltg_table_kernel(SimParams P, uint32_t
 // Count-threshold table (equal in-weights).  With c active in-arc pieces of
 // weight w_v, c * w_v > h exactly when c >= floor(h / w_v) + 1, so the table
 // holds k = floor(H(seed, LT, t, v) / w_v) + 1 per (node, trial), saturated at
-// 127 (a node evaluated from staged rows has at most 64 in-arc pieces, so a
-// saturated k is never reached either way).  The sweep compares bit-sliced
-// counts against it, so it is stored as complemented bit planes: for node v,
-// word group g (G = ceil(W / kRowWords) groups) and word x of the group, the
-// uint64 ((v*G + g)*kRowWords + x)*8 + b has bit t = NOT bit b of k for trial
-// 64*(g*kRowWords + x) + t (b < 7; plane 7 is all ones).
-// A wavefront fills 8 nodes x one word group: lane 8j+q draws node j's
-// blocks for trials 8q .. 8q+7 of each word and stages the bytes in LDS; then,
-// node by node, lane t holds its trial's 16 bytes as two 64-bit rows, and one
-// 64x64 bit transpose per row turns bit b of byte x into lane 8x+b, which is
-// the table's order, so each node's 1 KB is written contiguously.
-__device__ __forceinline__ uint32_t kmin_of(uint32_t h, uint32_t wv, uint32_t inv)
+// kmax = 2^S - 1 (at most 127), where S, the table's planes per word, is even
+// and large enough that kmax exceeds every count a node evaluated from staged
+// rows can reach (its in-arc pieces, at most 64): a saturated k is never met
+// either way.  The sweep compares bit-sliced counts against it, so it is
+// stored as complemented bit planes: for node v, word group g (G = ceil(W /
+// kRowWords) groups) and word x of the group, the uint64
+// ((v*G + g)*kRowWords + x)*S + b has bit t = NOT bit b of k for trial
+// 64*(g*kRowWords + x) + t.
+// A wavefront fills 8 nodes x one word group, eight words at a time: lane
+// 8j+q draws node j's blocks for trials 8q .. 8q+7 of each word and stages
+// the bytes in LDS (pitch 193 dwords per node and 3 per trial, so the byte
+// writes of a wavefront and the row reads fall in distinct banks); then, node
+// by node, lane t holds its trial's 8 bytes as a 64-bit row, and a 64x64 bit
+// transpose turns bit b of byte x into lane 8x+b, the table's order.
+__device__ __forceinline__ uint32_t kmin_of(uint32_t h, uint32_t wv, uint32_t inv, uint32_t kmax)
 {
-    if (wv == 0) return 127u;
     // floor(h / wv) from inv = floor(2^32 / wv) (wv >= 2): the estimate is
     // low by at most one
     uint32_t q = wv == 1 ? h : __umulhi(h, inv);
-    if (wv != 1 && h - q * wv >= wv) ++q;
-    return q >= 126u ? 127u : q + 1u;
+    q += h - q * wv >= wv ? 1u : 0u;
+    return wv == 0 ? kmax : (q < kmax - 1 ? q : kmax - 1) + 1;
 }
+
+constexpr uint32_t kKminNodePitch = 193;  // dwords per node in the staging area
 
 __global__ __launch_bounds__(kBlock) void ltg_kmin_kernel(SimParams P, uint64_t* __restrict__ kplanes)
 {
-    __shared__ uint8_t stage[kWaves][8 * 64 * kRowWords];
+    __shared__ uint32_t stage[kWaves][8 * kKminNodePitch];
     const uint64_t n = (uint64_t)P.n;
     const uint32_t W = P.W;
+    const uint32_t S = P.kp_stride;
+    const uint32_t kmax = S >= 7 ? 127u : (1u << S) - 1u;
     const uint64_t G = (W + kRowWords - 1) / kRowWords;
     const uint64_t items = ((n + 7) / 8) * G;
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t j = lane >> 3, q = lane & 7u;
-    uint8_t* S = stage[threadIdx.x >> 6];
+    uint32_t* St = stage[threadIdx.x >> 6];
+    uint8_t* Sb = reinterpret_cast<uint8_t*>(St);
     for (uint64_t it = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) >> 6; it < items; it += ((uint64_t)gridDim.x * kBlock) >> 6) {
         const uint64_t grp = it % G;
         const uint64_t v0 = (it / G) * 8;
         const uint64_t v = v0 + j;
         const uint32_t wv = v < n ? P.node_w[v] : 0u;
         const uint32_t inv = wv >= 2 ? (uint32_t)(0x100000000ull / wv) : 0u;
-        for (uint32_t x = 0; x < kRowWords; ++x) {
-            const uint32_t w = (uint32_t)grp * kRowWords + x;
-            uint32_t k[8];
-            if (v < n && w < W) {
-                const Block4 b = philox_block(v, (uint64_t)w * 8 + q, P.seed, kDomainLtNode);
+        for (uint32_t h8 = 0; h8 < kRowWords; h8 += 8) {
+            for (uint32_t x = 0; x < 8; ++x) {
+                const uint32_t w = (uint32_t)grp * kRowWords + h8 + x;
+                uint32_t k[8];
+                if (v < n && w < W) {
+                    const Block4 b = philox_block(v, (uint64_t)w * 8 + q, P.seed, kDomainLtNode);
 #pragma unroll
-                for (uint32_t i = 0; i < 8; ++i) k[i] = kmin_of(block_lane(b, i), wv, inv);
-            } else {
+                    for (uint32_t i = 0; i < 8; ++i) k[i] = kmin_of(block_lane(b, i), wv, inv, kmax);
+                } else {
 #pragma unroll
-                for (uint32_t i = 0; i < 8; ++i) k[i] = 127u;
+                    for (uint32_t i = 0; i < 8; ++i) k[i] = kmax;
+                }
+#pragma unroll
+                for (uint32_t i = 0; i < 8; ++i) Sb[(j * kKminNodePitch + 3 * (8 * q + i)) * 4 + x] = (uint8_t)k[i];
             }
-#pragma unroll
-            for (uint32_t i = 0; i < 8; ++i) S[(j * 64 + 8 * q + i) * kRowWords + x] = (uint8_t)k[i];
+            __builtin_amdgcn_wave_barrier();
+            for (uint32_t jj = 0; jj < 8; ++jj) {
+                if (v0 + jj >= n) break;
+                const uint32_t* src = St + jj * kKminNodePitch + 3 * lane;
+                const uint64_t r = wave_transpose64((uint64_t)src[0] | ((uint64_t)src[1] << 32), lane);
+                // lane 8x + b: plane b of word h8 + x
+                if ((lane & 7u) < S)
+                    kplanes[(((v0 + jj) * G + grp) * kRowWords + h8 + (lane >> 3)) * S + (lane & 7u)] = ~r;
+            }
+            __builtin_amdgcn_wave_barrier();
         }
-        __builtin_amdgcn_wave_barrier();
-        for (uint32_t jj = 0; jj < 8; ++jj) {
-            if (v0 + jj >= n) break;
-            const uint4 val = *reinterpret_cast<const uint4*>(S + (jj * 64 + lane) * kRowWords);
-            const uint64_t r0 = wave_transpose64((uint64_t)val.x | ((uint64_t)val.y << 32), lane);
-            const uint64_t r1 = wave_transpose64((uint64_t)val.z | ((uint64_t)val.w << 32), lane);
-            uint64_t* dst = kplanes + ((v0 + jj) * G + grp) * (kRowWords * 8);
-            dst[lane] = ~r0;
-            dst[64 + lane] = ~r1;
-        }
-        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -791,7 +809,9 @@ __device__ __forceinline__ uint64_t count_ge(const uint64_t (&c)[7], const uint6
 // fixpoint.  A sweep that follows one without change returns at once.
 // qcount[sw] counts the (node, word) pairs that changed.
 // kMode: 0 = threshold hashes drawn in the kernel, 1 = threshold table,
-// 2 = count-threshold table (equal in-weights; long rows draw hashes).
+// 2 = count-threshold table (equal in-weights) for batches of at most 64
+// in-arc pieces, 3 = the batches of one node with a longer row, hashes drawn
+// in the kernel (launched after kMode 2 in the same sweep).
 template <int kMode>
 __global__ __launch_bounds__(kBlock, 4) void ltg_sweep_kernel(SimParams P, uint32_t sw, uint32_t tau)
 {
@@ -822,13 +842,13 @@ __global__ __launch_bounds__(kBlock, 4) void ltg_sweep_kernel(SimParams P, uint3
     const uint64_t nwaves = ((uint64_t)gridDim.x * kBlock) >> 6;
     uint32_t changed = 0;
 
-    for (uint64_t bi = gwave; bi < P.nbatch; bi += nwaves) {
-        const uint32_t vf = uniform32(P.bfirst[bi]);
-        const uint32_t nn = uniform32(P.bfirst[bi + 1]) - vf;
+    // one batch, any threshold form: the in-arc pieces of the batch's nodes
+    // are found from the in-CSR; long rows gather one word at a time
+    auto batch_generic = [&](const uint32_t vf, const uint32_t nn) {
         const bool own = lane < nn;
         const uint64_t myv = own ? (uint64_t)vf + lane : 0ull;
         // a marked sweep skips batches none of whose nodes carries a mark
-        if (marked_only && __ballot(own && P.nmark[myv] >= min_mark) == 0) continue;
+        if (marked_only && __ballot(own && P.nmark[myv] >= min_mark) == 0) return;
         const int64_t kb = own ? P.in_off[myv] : 0;
         const uint32_t dg = own ? (uint32_t)(P.in_off[myv + 1] - kb) : 0u;
         uint32_t incl = dg;
@@ -839,7 +859,7 @@ __global__ __launch_bounds__(kBlock, 4) void ltg_sweep_kernel(SimParams P, uint3
         }
         const uint32_t pre_lane = incl - dg;
         const uint32_t total = uniform32(__shfl(incl, 7));
-        if (total == 0) continue;  // no in-weight: these nodes never join
+        if (total == 0) return;  // no in-weight: these nodes never join
         const bool big = total > 64;  // a single node with a long in-arc row
         uint32_t wn_lane = 0;
         if (own && P.lt_uniform) wn_lane = P.node_w[myv];
@@ -889,97 +909,6 @@ __global__ __launch_bounds__(kBlock, 4) void ltg_sweep_kernel(SimParams P, uint3
                 WT[lane] = wt;
                 __builtin_amdgcn_wave_barrier();
             };
-            if (kMode == 2 && !big) {
-                // count thresholds, bit-sliced: in pass p, lane 16i + x takes
-                // node 4p + i at word wg + x, adds the staged masks of the
-                // node's in-arcs into per-trial counts held as bit planes, and
-                // compares them with the node's threshold planes
-                uint64_t pq[2];
-                uint32_t passes = 0;
-#pragma unroll
-                for (uint32_t p = 0; p < 2; ++p) {
-                    const uint32_t j = 4 * p + (lane >> 4), x = lane & 15u;
-                    uint64_t pn = 0;
-                    if (j < nn && x < gw) {
-                        const uint64_t v = (uint64_t)vf + j;
-                        const uint32_t w = wg + x;
-                        pn = valid_mask(w, P.W, P.T) & ~load_relaxed(&P.Anm[v * W + w]);
-                        if (pn && marked_only && P.aux[v * W + w] < min_mark) pn = 0;
-                    }
-                    pq[p] = pn;
-                    passes |= (__ballot(pn != 0) != 0 ? 1u : 0u) << p;
-                }
-                passes = uniform32(passes);
-                if (passes == 0) continue;
-                stage_rows();
-                const uint64_t G = (W + kRowWords - 1) / kRowWords;
-                const uint64_t grp = wg / kRowWords;
-#pragma unroll
-                for (uint32_t p = 0; p < 2; ++p) {
-                    if (!((passes >> p) & 1u)) continue;
-                    const uint32_t x = lane & 15u, j = 4 * p + (lane >> 4);
-                    const uint64_t pend = pq[p];
-                    const uint64_t v = (uint64_t)vf + j;
-                    uint64_t k[8];
-                    if (pend) {
-                        const uint4* kp = reinterpret_cast<const uint4*>(P.kplanes + ((v * G + grp) * kRowWords + x) * 8);
-#pragma unroll
-                        for (uint32_t q = 0; q < 4; ++q) {
-                            const uint4 t = kp[q];
-                            k[2 * q] = (uint64_t)t.x | ((uint64_t)t.y << 32);
-                            k[2 * q + 1] = (uint64_t)t.z | ((uint64_t)t.w << 32);
-                        }
-                    } else {
-#pragma unroll
-                        for (uint32_t q = 0; q < 8; ++q) k[q] = 0;
-                    }
-                    const uint32_t lo = (uint32_t)__shfl((int)pre_lane, (int)j);
-                    const uint32_t dj = (uint32_t)__shfl((int)dg, (int)j);
-                    const uint32_t d = pend ? dj : 0u;
-                    // rows to add: the longest in-arc row among nodes with work
-                    const uint64_t bp = __ballot(pend != 0);
-                    uint32_t maxd = 0;
-#pragma unroll
-                    for (uint32_t i = 0; i < 4; ++i) {
-                        const uint32_t di = (uint32_t)__builtin_amdgcn_readlane((int)dg, (int)(4 * p + i));
-                        if ((bp >> (16 * i)) & 0xFFFFull) maxd = di > maxd ? di : maxd;
-                    }
-                    uint64_t c[7] = {0, 0, 0, 0, 0, 0, 0};
-                    for (uint32_t r = 0; r < maxd; r += 4) {
-                        // rows lo + r .. lo + r + 3; a lane whose row has
-                        // ended reads rows it masks (at most row 67)
-                        const uint32_t base = lo + r < 64u ? lo + r : 64u;
-                        const uint64_t* rr = R + base * kRowPitch + x;
-                        uint64_t in[4];
-#pragma unroll
-                        for (uint32_t u = 0; u < 4; ++u) in[u] = rr[u * kRowPitch];
-#pragma unroll
-                        for (uint32_t u = 0; u < 4; ++u) in[u] = r + u < d ? in[u] : 0ull;
-                        add4(c, in[0], in[1], in[2], in[3]);
-                    }
-                    const uint64_t dec = count_ge(c, k) & pend;
-                    const uint64_t db = __ballot(dec != 0);
-                    if (db == 0) continue;
-                    if (dec) atomic_or64(&P.Anm[v * W + wg + x], dec);
-                    changed += (uint32_t)__popcll(db);
-                    if (marks_now) {
-                        uint64_t mb = db;
-                        while (mb) {
-                            const uint32_t bit = (uint32_t)__builtin_ctzll(mb);
-                            mb &= mb - 1;
-                            const uint64_t vm = (uint64_t)vf + 4 * p + (bit >> 4);
-                            const uint32_t w = wg + (bit & 15u);
-                            for (int64_t e = P.off[vm] + lane; e < P.off[vm + 1]; e += 64) {
-                                const uint64_t t = P.idx[e];
-                                P.aux[t * W + w] = sw + 2;
-                                P.nmark[t] = sw + 2;
-                            }
-                        }
-                    }
-                }
-                __builtin_amdgcn_wave_barrier();
-                continue;
-            }
             // words of this group with a node to evaluate: lane 8j+x holds the
             // decidable trials of node j, word wg+x (pn0) and wg+x+8 (pn1)
             uint64_t pn0 = 0, pn1 = 0;
@@ -1092,6 +1021,192 @@ __global__ __launch_bounds__(kBlock, 4) void ltg_sweep_kernel(SimParams P, uint3
             }
             __builtin_amdgcn_wave_barrier();
         }
+    };
+    if (kMode == 2) {
+        // count thresholds, bit-sliced.  Batch descriptors come one batch
+        // ahead, and every load that depends only on the descriptor (node
+        // offsets, in-arc sources, own states, threshold planes) is issued
+        // before any is waited on, so a batch costs two dependent memory
+        // round trips (descriptor-dependent loads, then the source rows).
+        u32x4 dnext = {0, 0, 0, 0};
+        if (gwave < P.nbatch) dnext = P.bdesc[gwave];
+        for (uint64_t bi = gwave; bi < P.nbatch; bi += nwaves) {
+            const u32x4 dcur = dnext;
+            if (bi + nwaves < P.nbatch) dnext = P.bdesc[bi + nwaves];
+            const uint32_t vf = uniform32(dcur.x);
+            const uint32_t nn = uniform32(dcur.y) & 0xFFu;
+            const uint32_t total = uniform32(dcur.y) >> 8;
+            const uint64_t arc0 = (uint64_t)uniform32(dcur.z) | ((uint64_t)uniform32(dcur.w) << 32);
+            if (total == 0) continue;  // no in-weight: these nodes never join
+            if (total > 64) continue;  // a long row: the kMode 3 launch
+            if (marked_only && __ballot(lane < nn && P.nmark[(uint64_t)vf + lane] >= min_mark) == 0) continue;
+            for (uint32_t wg = 0; wg < P.W; wg += kRowWords) {
+                const uint32_t gw = P.W - wg < kRowWords ? P.W - wg : kRowWords;
+                const uint64_t G = (W + kRowWords - 1) / kRowWords;
+                const uint64_t grp = wg / kRowWords;
+                const uint32_t x = lane & 15u;
+                // Loads first, all from clamped (valid) addresses, results
+                // masked afterwards, so that none waits for another: this
+                // lane's in-arc source, in-CSR offsets of nodes 0 .. nn, own
+                // states of both passes (in pass p, lane 16i + x takes node
+                // 4p + i at word wg + x), and the threshold planes of pass 0
+                const uint32_t src = P.in_src32[arc0 + (lane < total ? lane : 0u)];
+                // (low halves suffice: only differences below 2^32 are used)
+                const uint32_t offl = reinterpret_cast<const uint32_t*>(P.in_off)[2 * ((uint64_t)vf + (lane <= nn ? lane : nn))];
+                const uint32_t xc = x < gw ? x : 0u;
+                bool live[2];
+                uint64_t own[2], mk[2] = {0, 0};
+#pragma unroll
+                for (uint32_t p = 0; p < 2; ++p) {
+                    const uint32_t j = 4 * p + (lane >> 4);
+                    live[p] = j < nn && x < gw;
+                    const uint64_t cell = (uint64_t)(vf + (j < nn ? j : 0u)) * W + wg + xc;
+                    own[p] = P.Anm[cell];
+                    if (marked_only) mk[p] = P.aux[cell];
+                }
+                uint64_t pq[2];
+                uint32_t passes = 0;
+                auto pending = [&]() {
+#pragma unroll
+                    for (uint32_t p = 0; p < 2; ++p) {
+                        const uint64_t pn = live[p] ? valid_mask(wg + x, P.W, P.T) & ~own[p] : 0ull;
+                        pq[p] = marked_only && mk[p] < min_mark ? 0ull : pn;
+                        passes |= (__ballot(pq[p] != 0) != 0 ? 1u : 0u) << p;
+                    }
+                    passes = uniform32(passes);
+                };
+                // a marked sweep evaluates few batches: it checks for pending
+                // trials before loading rows; a dense sweep nearly always
+                // needs them and loads them at once
+                if (marked_only) {
+                    pending();
+                    if (passes == 0) continue;
+                }
+                // complemented threshold planes: 64 bytes from the lane's
+                // first plane (the table is padded so this stays inside it);
+                // planes beyond the table's stride are those of a zero bit.
+                // The table streams through once per sweep, so its loads are
+                // non-temporal
+                auto load_planes = [&](uint32_t p, uint64_t (&k)[8]) {
+                    const uint32_t j = 4 * p + (lane >> 4);
+                    const u32x4* kp = reinterpret_cast<const u32x4*>(
+                        P.kplanes + (((uint64_t)(vf + (j < nn ? j : 0u)) * G + grp) * kRowWords + xc) * P.kp_stride);
+#pragma unroll
+                    for (uint32_t q = 0; q < 4; ++q) {
+                        const u32x4 t = __builtin_nontemporal_load(kp + q);
+                        k[2 * q] = (uint64_t)t.x | ((uint64_t)t.y << 32);
+                        k[2 * q + 1] = (uint64_t)t.z | ((uint64_t)t.w << 32);
+                    }
+#pragma unroll
+                    for (uint32_t b = 0; b < 8; ++b) k[b] = b < P.kp_stride ? k[b] : ~0ull;
+                };
+                uint64_t k0[8];
+                load_planes(0, k0);
+                // stage the source rows of this word group: R[i][x] = state of
+                // in-arc i's source at word wg + x.  Plain loads: a mask read
+                // stale within a sweep only delays a join to the next sweep,
+                // and a sweep without joins saw the state it started from
+                {
+                    const uint64_t* rp = P.Anm + (uint64_t)src * W + wg;
+                    __builtin_amdgcn_wave_barrier();
+                    if ((W & 1) == 0 && gw == kRowWords) {
+                        uint64_t row[kRowWords];
+                        const uint4* rp4 = reinterpret_cast<const uint4*>(rp);
+#pragma unroll
+                        for (uint32_t y = 0; y < kRowWords / 2; ++y) {
+                            const uint4 q = rp4[y];
+                            row[2 * y] = (uint64_t)q.x | ((uint64_t)q.y << 32);
+                            row[2 * y + 1] = (uint64_t)q.z | ((uint64_t)q.w << 32);
+                        }
+#pragma unroll
+                        for (uint32_t y = 0; y < kRowWords; ++y) R[lane * kRowPitch + y] = lane < total ? row[y] : 0ull;
+                    } else {
+                        // odd word count or a short last group: word by word
+#pragma unroll 1
+                        for (uint32_t y = 0; y < kRowWords; ++y) {
+                            const uint64_t m = rp[y < gw ? y : 0u];
+                            R[lane * kRowPitch + y] = lane < total && y < gw ? m : 0ull;
+                        }
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                }
+                if (!marked_only) {
+                    pending();
+                    if (passes == 0) continue;
+                }
+#pragma unroll
+                for (uint32_t p = 0; p < 2; ++p) {
+                    if (!((passes >> p) & 1u)) continue;
+                    const uint32_t j = 4 * p + (lane >> 4);
+                    const uint64_t pend = pq[p];
+                    const uint64_t v = (uint64_t)vf + j;
+                    uint64_t k[8];
+                    if (p == 0) {
+#pragma unroll
+                        for (uint32_t q = 0; q < 8; ++q) k[q] = k0[q];
+                    } else {
+                        load_planes(1, k);
+                    }
+                    // node j's in-arc rows: lo .. lo + d - 1
+                    const uint32_t oj = (uint32_t)__shfl((int)offl, (int)j);
+                    const uint32_t oj1 = (uint32_t)__shfl((int)offl, (int)(j + 1));
+                    const uint32_t lo = oj - (uint32_t)arc0;
+                    const uint32_t dj = oj1 - oj;
+                    const uint32_t d = pend ? dj : 0u;
+                    // rows to add: the longest in-arc row among nodes with a
+                    // pending trial in any word (lanes 16i .. 16i + 15 share
+                    // node 4p + i)
+                    const uint64_t bp = __ballot(pend != 0);
+                    uint32_t maxd = 0;
+#pragma unroll
+                    for (uint32_t i = 0; i < 4; ++i) {
+                        const uint32_t di = (uint32_t)__builtin_amdgcn_readlane((int)dj, (int)(16 * i));
+                        if ((bp >> (16 * i)) & 0xFFFFull) maxd = di > maxd ? di : maxd;
+                    }
+                    uint64_t c[7] = {0, 0, 0, 0, 0, 0, 0};
+                    for (uint32_t r = 0; r < maxd; r += 4) {
+                        // rows lo + r .. lo + r + 3; a lane whose row has
+                        // ended reads rows it masks (at most row 67)
+                        const uint32_t base = lo + r < 64u ? lo + r : 64u;
+                        const uint64_t* rr = R + base * kRowPitch + x;
+                        uint64_t in[4];
+#pragma unroll
+                        for (uint32_t u = 0; u < 4; ++u) in[u] = rr[u * kRowPitch];
+#pragma unroll
+                        for (uint32_t u = 0; u < 4; ++u) in[u] = r + u < d ? in[u] : 0ull;
+                        add4(c, in[0], in[1], in[2], in[3]);
+                    }
+                    const uint64_t dec = count_ge(c, k) & pend;
+                    const uint64_t db = __ballot(dec != 0);
+                    if (db == 0) continue;
+                    if (dec) atomic_or64(&P.Anm[v * W + wg + x], dec);
+                    changed += (uint32_t)__popcll(db);
+                    if (marks_now) {
+                        uint64_t mb = db;
+                        while (mb) {
+                            const uint32_t bit = (uint32_t)__builtin_ctzll(mb);
+                            mb &= mb - 1;
+                            const uint64_t vm = (uint64_t)vf + 4 * p + (bit >> 4);
+                            const uint32_t w = wg + (bit & 15u);
+                            for (int64_t e = P.off[vm] + lane; e < P.off[vm + 1]; e += 64) {
+                                const uint64_t t = P.idx[e];
+                                P.aux[t * W + w] = sw + 2;
+                                P.nmark[t] = sw + 2;
+                            }
+                        }
+                    }
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+    } else if (kMode == 3) {
+        for (uint64_t i = gwave; i < P.nbig; i += nwaves) {
+            const uint32_t bi = uniform32(P.bigb[i]);
+            batch_generic(uniform32(P.bfirst[bi]), uniform32(P.bfirst[bi + 1]) - uniform32(P.bfirst[bi]));
+        }
+    } else {
+        for (uint64_t bi = gwave; bi < P.nbatch; bi += nwaves)
+            batch_generic(uniform32(P.bfirst[bi]), uniform32(P.bfirst[bi + 1]) - uniform32(P.bfirst[bi]));
     }
     if (changed && lane == 0) atomicAdd(&P.qcount[sw], changed);
 }

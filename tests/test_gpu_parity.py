@@ -199,6 +199,20 @@ def test_lt_grid_count_thresholds_over_several_word_groups(ims, T):
     run_both(ims, "lt", g.n, g.offsets, g.indices, param, seeds, T, 29, opts=opts)
 
 
+@pytest.mark.parametrize("alpha", [0.0, 1.0])
+def test_lt_grid_count_thresholds_with_long_rows(ims, alpha):
+    """Count-threshold sweeps on a graph where 24 nodes have more than 64
+    in-arc pieces (Barabasi-Albert hubs, in-degree up to 280): those batches
+    are evaluated by a second launch in every sweep, with marking always off
+    or always on."""
+    g = synth.barabasi_albert(5000, 4, seed=35)
+    assert int(np.bincount(g.indices, minlength=g.n).max()) > 64
+    param = synth.weighted_cascade(g)
+    seeds = synth.random_seeds(g.n, 10, seed=36)
+    opts = ims.Opts(shape=2, blocks_per_cu=0, alpha=alpha, profile=0, test_flags=0)
+    run_both(ims, "lt", g.n, g.offsets, g.indices, param, seeds, 300, 31, opts=opts)
+
+
 @pytest.mark.parametrize("model", ["ic", "lt"])
 def test_sets_equal_single_runs_and_oracle(ims, model):
     """Many seed sets at once (common random numbers) == each set alone."""
