@@ -508,7 +508,10 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
     IMS_HIP(hipMemcpyAsync(g->d_seed_pre, seed_pre.data(), seed_pre.size() * sizeof(uint64_t), hipMemcpyHostToDevice, s));
 
     uint64_t* A = active_bits ? active_bits : (uint64_t*)g->A.p;
-    if ((rc = fill_async<uint64_t>(A, cells, 0ull, s))) return rc;
+    // the LT grid shape keeps its state node-major and writes A (when asked
+    // for) from it at the end
+    const bool ltg = shape == 2 && g->model == IMS_MODEL_LT;
+    if (!ltg && (rc = fill_async<uint64_t>(A, cells, 0ull, s))) return rc;
     if (g->zero_dirty) {
         for (auto& b : g->N)
             if (b.p && (rc = fill_async<uint8_t>((uint8_t*)b.p, b.bytes, 0, s))) return rc;
@@ -611,7 +614,7 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
             const uint64_t work = std::max<uint64_t>(seed_pre.back(), (uint64_t)P.n_seeds * W);
             hipLaunchKernelGGL(imsim::ltg_seed_kernel,
                                dim3((uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(blocks, (work + imsim::kBlock - 1) / imsim::kBlock))),
-                               dim3(imsim::kBlock), 0, s, P, (const uint64_t*)g->d_seed_pre);
+                               dim3(imsim::kBlock), 0, s, P, (const uint64_t*)g->d_seed_pre, P.seed_arcs * W < tau ? 1 : 0);
             IMS_HIP(hipGetLastError());
         }
         // steps in batches; a step after the last productive one returns at
@@ -660,8 +663,9 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
         IMS_HIP(hipMemcpyAsync(g->d_status, &steps, sizeof steps, hipMemcpyHostToDevice, s));
         IMS_HIP(hipStreamSynchronize(s));
         if (g->model == IMS_MODEL_LT && cells > 0) {
-            hipLaunchKernelGGL(imsim::ltg_to_word_major, dim3((uint32_t)std::min<uint64_t>((cells + imsim::kBlock - 1) / imsim::kBlock, 65536)),
-                               dim3(imsim::kBlock), 0, s, (const uint64_t*)P.Anm, A, g->n, W);
+            hipLaunchKernelGGL(imsim::ltg_finish_kernel, dim3((uint32_t)std::min<uint64_t>(g->cus, ((uint64_t)g->n + 255) / 256)),
+                               dim3(imsim::kBlock), 0, s, (const uint64_t*)P.Anm, active_bits, g->n, W, n_trials, trial_counts,
+                               node_counts, (unsigned long long*)total);
             IMS_HIP(hipGetLastError());
         }
     }
@@ -671,7 +675,7 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
     }
     g->last_shape = (uint32_t)shape;
 
-    if (n > 0) {
+    if (n > 0 && !(ltg && cells > 0)) {
         const uint64_t nblk = std::min<uint64_t>((n + imsim::kBlock - 1) / imsim::kBlock, 1024);
         hipLaunchKernelGGL(imsim::reduce_trial_counts, dim3((unsigned)nblk, W), dim3(imsim::kBlock), 0, s, A, g->n, n_trials,
                            trial_counts);

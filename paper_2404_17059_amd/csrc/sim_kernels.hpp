@@ -628,7 +628,7 @@ __device__ __forceinline__ uint64_t wave_transpose64(uint64_t x, uint32_t lane)
 
 // Seeds are active in every trial; their out-neighbours are marked (value 1)
 // for sweep 0.  seed_arc_pre[i] = number of seed out-arcs before seed i.
-__global__ __launch_bounds__(kBlock) void ltg_seed_kernel(SimParams P, const uint64_t* __restrict__ seed_arc_pre)
+__global__ __launch_bounds__(kBlock) void ltg_seed_kernel(SimParams P, const uint64_t* __restrict__ seed_arc_pre, int mark)
 {
     const uint64_t W = P.W;
     const uint64_t gt = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -638,7 +638,7 @@ __global__ __launch_bounds__(kBlock) void ltg_seed_kernel(SimParams P, const uin
         const uint32_t w = (uint32_t)(i % W);
         P.Anm[(uint64_t)s * W + w] = valid_mask(w, P.W, P.T);
     }
-    const uint64_t total = seed_arc_pre[P.n_seeds];
+    const uint64_t total = mark ? seed_arc_pre[P.n_seeds] : 0;
     for (uint64_t q = gt; q < total; q += nt) {
         uint32_t lo = 0, hi = P.n_seeds;  // last seed with seed_arc_pre[i] <= q
         while (hi - lo > 1) {
@@ -803,8 +803,9 @@ __device__ __forceinline__ uint64_t count_ge(const uint64_t (&c)[7], const uint6
 // node that joins then stamps its out-neighbours with sw + 2 in aux (node-
 // major, per word) and in nmark (per node, so a marked sweep can skip a batch
 // after one load).  A sweep that follows a marking sweep evaluates only nodes stamped
-// >= sw + 1 (sweep 0 follows the seed marks); any other sweep evaluates every
-// node with an inactive trial.  A node none of whose in-neighbours changed
+// >= sw + 1 (sweep 0 follows the seeding, which marks the seeds' out-
+// neighbours when they number fewer than tau); any other sweep evaluates
+// every node with an inactive trial.  A node none of whose in-neighbours changed
 // since its last evaluation cannot change, so both forms reach the same
 // fixpoint.  A sweep that follows one without change returns at once.
 // qcount[sw] counts the (node, word) pairs that changed.
@@ -824,12 +825,14 @@ __global__ __launch_bounds__(kBlock, 4) void ltg_sweep_kernel(SimParams P, uint3
         return;
     }
     // changes of sweep x; before sweep 0, the seeds' out-arcs times the words
-    // stand for the pairs sweep 0 may change
+    // stand for the pairs sweep 0 may change (x = -1) and for the seeding
+    // itself (x = -2: the seeds mark their out-neighbours when that is below
+    // tau, and sweep 0 then evaluates only those)
     auto changes = [&](int64_t x) -> uint64_t {
         return x < 0 ? P.seed_arcs * P.W : (uint64_t)load_relaxed32(&P.qcount[x]);
     };
     const bool marks_now = changes((int64_t)sw - 1) < tau;
-    const bool marked_only = sw == 0 ? true : changes((int64_t)sw - 2) < tau;
+    const bool marked_only = changes((int64_t)sw - 2) < tau;
     const uint32_t min_mark = sw + 1;
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = threadIdx.x >> 6;
@@ -1209,17 +1212,6 @@ __global__ __launch_bounds__(kBlock, 4) void ltg_sweep_kernel(SimParams P, uint3
             batch_generic(uniform32(P.bfirst[bi]), uniform32(P.bfirst[bi + 1]) - uniform32(P.bfirst[bi]));
     }
     if (changed && lane == 0) atomicAdd(&P.qcount[sw], changed);
-}
-
-// Word-major copy of the node-major state: A[w*n + v] = Anm[v*W + w].
-__global__ __launch_bounds__(kBlock) void ltg_to_word_major(const uint64_t* __restrict__ Anm, uint64_t* __restrict__ A, int64_t n,
-                                                          uint32_t W)
-{
-    const uint64_t total = (uint64_t)n * W;
-    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += (uint64_t)gridDim.x * kBlock) {
-        const uint64_t w = i / (uint64_t)n, v = i % (uint64_t)n;
-        A[i] = Anm[v * W + w];
-    }
 }
 
 // ====================================================== word-local shape
@@ -1642,6 +1634,80 @@ __global__ __launch_bounds__(kTaskBlock, 2) void batch_kernel(const BatchItem* _
 
 // trial_counts[64w + b] += number of nodes with bit b of A[w*n + v] set.
 // Grid: (blocks over nodes, W).  Lane b counts trial 64w + b.
+// LT grid shape, last step: from the node-major state, in one pass over it,
+// the per-node counts (and their total), the per-trial counts and, when asked
+// for, the word-major copy A[w*n + v].  A wavefront takes 64 nodes at a time
+// (lane = node) and one group of up to 16 words: a 64x64 bit transpose of each
+// word turns "node v active in trial t" into lane t's 64-bit row over the
+// nodes, whose popcount adds to trial t's count.  Per-trial sums meet in LDS
+// before one atomic add per (block, trial).
+__global__ __launch_bounds__(kBlock) void ltg_finish_kernel(const uint64_t* __restrict__ Anm, uint64_t* __restrict__ A, int64_t n,
+                                                          uint32_t W, uint32_t T, uint32_t* __restrict__ trial_counts,
+                                                          uint32_t* __restrict__ node_counts, unsigned long long* __restrict__ total)
+{
+    __shared__ uint32_t part[kWaves][kRowWords][64];
+    __shared__ unsigned long long tpart[kWaves];
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = threadIdx.x >> 6;
+    const uint64_t gwave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * kBlock) >> 6;
+    const uint64_t ntiles = ((uint64_t)n + 63) / 64;
+    unsigned long long sum = 0;
+    for (uint32_t wg = 0; wg < W; wg += kRowWords) {
+        const uint32_t gw = W - wg < kRowWords ? W - wg : kRowWords;
+        uint32_t acc[kRowWords];
+#pragma unroll
+        for (uint32_t x = 0; x < kRowWords; ++x) acc[x] = 0;
+        for (uint64_t tile = gwave; tile < ntiles; tile += nwaves) {
+            const uint64_t v = tile * 64 + lane;
+            const bool ok = v < (uint64_t)n;
+            uint64_t wd[kRowWords];
+            if ((W & 1) == 0 && gw == kRowWords) {
+                const uint4* p4 = reinterpret_cast<const uint4*>(Anm + (ok ? v : 0) * W + wg);
+#pragma unroll
+                for (uint32_t y = 0; y < kRowWords / 2; ++y) {
+                    const uint4 q = p4[y];
+                    wd[2 * y] = ok ? (uint64_t)q.x | ((uint64_t)q.y << 32) : 0ull;
+                    wd[2 * y + 1] = ok ? (uint64_t)q.z | ((uint64_t)q.w << 32) : 0ull;
+                }
+            } else {
+#pragma unroll
+                for (uint32_t x = 0; x < kRowWords; ++x) wd[x] = ok && x < gw ? Anm[v * W + wg + x] : 0ull;
+            }
+            uint32_t c = 0;
+#pragma unroll
+            for (uint32_t x = 0; x < kRowWords; ++x) {
+                if (x >= gw) break;
+                c += (uint32_t)__popcll(wd[x]);
+                if (A && ok) A[(uint64_t)(wg + x) * (uint64_t)n + v] = wd[x];
+                acc[x] += (uint32_t)__popcll(wave_transpose64(wd[x], lane));
+            }
+            if (ok && node_counts) node_counts[v] = (wg == 0 ? 0u : node_counts[v]) + c;
+            sum += c;
+        }
+#pragma unroll
+        for (uint32_t x = 0; x < kRowWords; ++x) part[wave][x][lane] = acc[x];
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < kRowWords * 64; i += kBlock) {
+            const uint32_t x = i >> 6, t = i & 63u;
+            uint32_t s2 = 0;
+#pragma unroll
+            for (int q = 0; q < kWaves; ++q) s2 += part[q][x][t];
+            const uint64_t trial = (uint64_t)(wg + x) * 64 + t;
+            if (s2 && x < gw && trial < T) atomicAdd(&trial_counts[trial], s2);
+        }
+        __syncthreads();
+    }
+    for (int o = 32; o > 0; o >>= 1) sum += __shfl_down(sum, o);
+    if (lane == 0) tpart[wave] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long s2 = 0;
+        for (int q = 0; q < kWaves; ++q) s2 += tpart[q];
+        if (s2) atomicAdd(total, s2);
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void reduce_trial_counts(const uint64_t* __restrict__ A, int64_t n, uint32_t T,
                                                               uint32_t* __restrict__ trial_counts)
 {
