@@ -421,6 +421,20 @@ int ims_graph_info(const ims_graph* g, int64_t* n, int64_t* m, int* model)
 
 namespace {
 
+// Workgroups of `kernel` (kBlock threads) resident on the whole device at
+// once: a grid of exactly this size runs in one round, with no second round
+// of workgroups trailing behind.
+template <typename K>
+uint32_t resident_blocks(K kernel, uint32_t cus)
+{
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, imsim::kBlock, 0) != hipSuccess || per_cu < 1) {
+        (void)hipGetLastError();
+        per_cu = 1;
+    }
+    return (uint32_t)per_cu * cus;
+}
+
 // One simulation; with level_counts the word-local IC shape also counts the
 // nodes first activated at every level of every trial.
 int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_t n_trials, uint64_t rng_seed,
@@ -588,8 +602,15 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
             hipLaunchKernelGGL((imsim::word_kernel<false, true>), dim3(blocks), dim3(imsim::kTaskBlock), 0, s, P, n);
         IMS_HIP(hipGetLastError());
     } else {
-        const int per_cu = opts && opts->blocks_per_cu > 0 ? opts->blocks_per_cu : 8;
+        // IC: 4 workgroups per compute unit by default (measured on the
+        // benchmark graphs: up to 20% faster than 8, never slower than 1-3)
+        const int per_cu = opts && opts->blocks_per_cu > 0 ? opts->blocks_per_cu : 4;
         const uint32_t blocks = (uint32_t)(g->cus * per_cu);
+        // LT: by default every kernel of the run gets exactly its resident
+        // grid (measured on the 1M-node count form: 13.0 ms against 15.7 ms
+        // at 8 workgroups per compute unit)
+        const bool fixed = opts && opts->blocks_per_cu > 0;
+        auto lt_blocks = [&](auto kernel) -> uint32_t { return fixed ? blocks : resident_blocks(kernel, (uint32_t)g->cus); };
         if ((rc = fill_async<uint32_t>(g->d_qcount, g->cap, 0u, s))) return rc;
         const uint32_t tau = opts && opts->alpha > 0.0 ? (uint32_t)std::min<double>(opts->alpha * (double)cells, 4e9)
                                                        : (uint32_t)std::min<uint64_t>(cells / 32 + 1, 0xFFFFFFFFull);
@@ -604,11 +625,13 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
             if ((rc = fill_async<uint32_t>((uint32_t*)g->nmark.p, (uint64_t)g->n, 0u, s))) return rc;
             if (lt_mode == 1) {
                 P.th32 = (const uint32_t*)g->thp.p;
-                hipLaunchKernelGGL(imsim::ltg_table_kernel, dim3(blocks), dim3(imsim::kBlock), 0, s, P, (uint32_t*)g->thp.p);
+                hipLaunchKernelGGL(imsim::ltg_table_kernel, dim3(lt_blocks(imsim::ltg_table_kernel)), dim3(imsim::kBlock), 0, s, P,
+                                   (uint32_t*)g->thp.p);
                 IMS_HIP(hipGetLastError());
             } else if (lt_mode == 2) {
                 P.kplanes = (const uint64_t*)g->thp.p;
-                hipLaunchKernelGGL(imsim::ltg_kmin_kernel, dim3(blocks), dim3(imsim::kBlock), 0, s, P, (uint64_t*)g->thp.p);
+                hipLaunchKernelGGL(imsim::ltg_kmin_kernel, dim3(lt_blocks(imsim::ltg_kmin_kernel)), dim3(imsim::kBlock), 0, s, P,
+                                   (uint64_t*)g->thp.p);
                 IMS_HIP(hipGetLastError());
             }
             const uint64_t work = std::max<uint64_t>(seed_pre.back(), (uint64_t)P.n_seeds * W);
@@ -616,6 +639,13 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
                                dim3((uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(blocks, (work + imsim::kBlock - 1) / imsim::kBlock))),
                                dim3(imsim::kBlock), 0, s, P, (const uint64_t*)g->d_seed_pre, P.seed_arcs * W < tau ? 1 : 0);
             IMS_HIP(hipGetLastError());
+        }
+        uint32_t sweep_blocks = blocks, big_blocks = blocks;
+        if (g->model == IMS_MODEL_LT) {
+            sweep_blocks = lt_mode == 2   ? lt_blocks(imsim::ltg_sweep_kernel<2>)
+                           : lt_mode == 1 ? lt_blocks(imsim::ltg_sweep_kernel<1>)
+                                          : lt_blocks(imsim::ltg_sweep_kernel<0>);
+            big_blocks = lt_blocks(imsim::ltg_sweep_kernel<3>);
         }
         // steps in batches; a step after the last productive one returns at
         // once, so only the end of each batch is read back
@@ -629,16 +659,16 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
                 else
                 {
                     if (lt_mode == 2) {
-                        hipLaunchKernelGGL(imsim::ltg_sweep_kernel<2>, dim3(blocks), dim3(imsim::kBlock), 0, s, P, st, tau);
+                        hipLaunchKernelGGL(imsim::ltg_sweep_kernel<2>, dim3(sweep_blocks), dim3(imsim::kBlock), 0, s, P, st, tau);
                         if (g->nbig)
                             hipLaunchKernelGGL(imsim::ltg_sweep_kernel<3>,
-                                               dim3(std::min<uint32_t>(blocks, (g->nbig + imsim::kWaves - 1) / imsim::kWaves)),
+                                               dim3(std::min<uint32_t>(big_blocks, (g->nbig + imsim::kWaves - 1) / imsim::kWaves)),
                                                dim3(imsim::kBlock), 0, s, P, st, tau);
                     }
                     else if (lt_mode == 1)
-                        hipLaunchKernelGGL(imsim::ltg_sweep_kernel<1>, dim3(blocks), dim3(imsim::kBlock), 0, s, P, st, tau);
+                        hipLaunchKernelGGL(imsim::ltg_sweep_kernel<1>, dim3(sweep_blocks), dim3(imsim::kBlock), 0, s, P, st, tau);
                     else
-                        hipLaunchKernelGGL(imsim::ltg_sweep_kernel<0>, dim3(blocks), dim3(imsim::kBlock), 0, s, P, st, tau);
+                        hipLaunchKernelGGL(imsim::ltg_sweep_kernel<0>, dim3(sweep_blocks), dim3(imsim::kBlock), 0, s, P, st, tau);
                 }
             }
             IMS_HIP(hipGetLastError());
