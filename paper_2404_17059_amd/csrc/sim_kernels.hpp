@@ -1026,37 +1026,64 @@ __global__ __launch_bounds__(kBlock, 4) void ltg_sweep_kernel(SimParams P, uint3
         }
     };
     if (kMode == 2) {
-        // count thresholds, bit-sliced.  Batch descriptors come one batch
-        // ahead, and every load that depends only on the descriptor (node
-        // offsets, in-arc sources, own states, threshold planes) is issued
-        // before any is waited on, so a batch costs two dependent memory
-        // round trips (descriptor-dependent loads, then the source rows).
-        u32x4 dnext = {0, 0, 0, 0};
-        if (gwave < P.nbatch) dnext = P.bdesc[gwave];
+        // count thresholds, bit-sliced.  Batch descriptors come two batches
+        // ahead, and what decides whether a batch has work comes one batch
+        // ahead: in a dense sweep over at most 16 words the own states of its
+        // nodes, in a marked sweep their marks.  So a batch starts knowing its
+        // pending trials (dense) and only lanes with pending trials load
+        // threshold planes.  The loads that depend only on the descriptor
+        // (node offsets, in-arc sources, planes) are issued before any is
+        // waited on, and the source rows follow: two dependent memory round
+        // trips per batch with work.
+        const bool pre = !marked_only && P.W <= kRowWords;
+        const uint32_t x = lane & 15u;
+        auto own_of = [&](const u32x4 d, uint64_t (&o)[2]) {
+            const uint32_t dvf = uniform32(d.x), dnn = uniform32(d.y) & 0xFFu;
+            const uint32_t xc = x < P.W ? x : 0u;
+#pragma unroll
+            for (uint32_t p = 0; p < 2; ++p) {
+                const uint32_t j = 4 * p + (lane >> 4);
+                o[p] = P.Anm[(uint64_t)(dvf + (j < dnn ? j : 0u)) * W + xc];
+            }
+        };
+        auto mark_of = [&](const u32x4 d) -> uint32_t {
+            const uint32_t dvf = uniform32(d.x), dnn = uniform32(d.y) & 0xFFu;
+            return P.nmark[(uint64_t)dvf + (lane < dnn ? lane : 0u)];
+        };
+        u32x4 dA = {0, 0, 0, 0}, dB = {0, 0, 0, 0};
+        uint64_t oA[2] = {0, 0};
+        uint32_t mA = 0;
+        if (gwave < P.nbatch) {
+            dA = P.bdesc[gwave];
+            if (pre) own_of(dA, oA);
+            if (marked_only) mA = mark_of(dA);
+        }
+        if (gwave + nwaves < P.nbatch) dB = P.bdesc[gwave + nwaves];
         for (uint64_t bi = gwave; bi < P.nbatch; bi += nwaves) {
-            const u32x4 dcur = dnext;
-            if (bi + nwaves < P.nbatch) dnext = P.bdesc[bi + nwaves];
+            const u32x4 dcur = dA;
+            const uint64_t oc0 = oA[0], oc1 = oA[1];
+            const uint32_t mc = mA;
+            dA = dB;
+            if (bi + 2 * nwaves < P.nbatch) dB = P.bdesc[bi + 2 * nwaves];
+            if (bi + nwaves < P.nbatch) {
+                if (pre) own_of(dA, oA);
+                if (marked_only) mA = mark_of(dA);
+            }
             const uint32_t vf = uniform32(dcur.x);
             const uint32_t nn = uniform32(dcur.y) & 0xFFu;
             const uint32_t total = uniform32(dcur.y) >> 8;
             const uint64_t arc0 = (uint64_t)uniform32(dcur.z) | ((uint64_t)uniform32(dcur.w) << 32);
             if (total == 0) continue;  // no in-weight: these nodes never join
             if (total > 64) continue;  // a long row: the kMode 3 launch
-            if (marked_only && __ballot(lane < nn && P.nmark[(uint64_t)vf + lane] >= min_mark) == 0) continue;
+            if (marked_only && __ballot(lane < nn && mc >= min_mark) == 0) continue;
             for (uint32_t wg = 0; wg < P.W; wg += kRowWords) {
                 const uint32_t gw = P.W - wg < kRowWords ? P.W - wg : kRowWords;
                 const uint64_t G = (W + kRowWords - 1) / kRowWords;
                 const uint64_t grp = wg / kRowWords;
-                const uint32_t x = lane & 15u;
-                // Loads first, all from clamped (valid) addresses, results
-                // masked afterwards, so that none waits for another: this
-                // lane's in-arc source, in-CSR offsets of nodes 0 .. nn, own
-                // states of both passes (in pass p, lane 16i + x takes node
-                // 4p + i at word wg + x), and the threshold planes of pass 0
-                const uint32_t src = P.in_src32[arc0 + (lane < total ? lane : 0u)];
-                // (low halves suffice: only differences below 2^32 are used)
-                const uint32_t offl = reinterpret_cast<const uint32_t*>(P.in_off)[2 * ((uint64_t)vf + (lane <= nn ? lane : nn))];
                 const uint32_t xc = x < gw ? x : 0u;
+                // own states of both passes (in pass p, lane 16i + x takes
+                // node 4p + i at word wg + x), from clamped addresses with the
+                // results masked afterwards
                 bool live[2];
                 uint64_t own[2], mk[2] = {0, 0};
 #pragma unroll
@@ -1064,8 +1091,12 @@ __global__ __launch_bounds__(kBlock, 4) void ltg_sweep_kernel(SimParams P, uint3
                     const uint32_t j = 4 * p + (lane >> 4);
                     live[p] = j < nn && x < gw;
                     const uint64_t cell = (uint64_t)(vf + (j < nn ? j : 0u)) * W + wg + xc;
-                    own[p] = P.Anm[cell];
-                    if (marked_only) mk[p] = P.aux[cell];
+                    if (pre) {
+                        own[p] = p ? oc1 : oc0;
+                    } else {
+                        own[p] = P.Anm[cell];
+                        if (marked_only) mk[p] = P.aux[cell];
+                    }
                 }
                 uint64_t pq[2];
                 uint32_t passes = 0;
@@ -1078,19 +1109,28 @@ __global__ __launch_bounds__(kBlock, 4) void ltg_sweep_kernel(SimParams P, uint3
                     }
                     passes = uniform32(passes);
                 };
-                // a marked sweep evaluates few batches: it checks for pending
-                // trials before loading rows; a dense sweep nearly always
-                // needs them and loads them at once
-                if (marked_only) {
+                // known pending trials (prefetched, or a marked sweep's own
+                // round trip): decide now; otherwise (a dense sweep over more
+                // than 16 words) load rows and planes at once and decide after
+                const bool known = pre || marked_only;
+                if (known) {
                     pending();
                     if (passes == 0) continue;
                 }
+                // this lane's in-arc source and the in-CSR offsets of nodes
+                // 0 .. nn (low halves suffice: only differences below 2^32
+                // are used)
+                const uint32_t src = P.in_src32[arc0 + (lane < total ? lane : 0u)];
+                const uint32_t offl = reinterpret_cast<const uint32_t*>(P.in_off)[2 * ((uint64_t)vf + (lane <= nn ? lane : nn))];
                 // complemented threshold planes: 64 bytes from the lane's
                 // first plane (the table is padded so this stays inside it);
                 // planes beyond the table's stride are those of a zero bit.
                 // The table streams through once per sweep, so its loads are
                 // non-temporal
                 auto load_planes = [&](uint32_t p, uint64_t (&k)[8]) {
+#pragma unroll
+                    for (uint32_t q = 0; q < 8; ++q) k[q] = ~0ull;
+                    if (known && pq[p] == 0) return;
                     const uint32_t j = 4 * p + (lane >> 4);
                     const u32x4* kp = reinterpret_cast<const u32x4*>(
                         P.kplanes + (((uint64_t)(vf + (j < nn ? j : 0u)) * G + grp) * kRowWords + xc) * P.kp_stride);
@@ -1133,7 +1173,7 @@ __global__ __launch_bounds__(kBlock, 4) void ltg_sweep_kernel(SimParams P, uint3
                     }
                     __builtin_amdgcn_wave_barrier();
                 }
-                if (!marked_only) {
+                if (!known) {
                     pending();
                     if (passes == 0) continue;
                 }
