@@ -100,7 +100,7 @@ typedef struct ims_opts {
     int32_t blocks_per_cu; /* workgroups per compute unit; 0 = auto */
     double alpha;          /* LT grid shape: a sweep marks out-neighbours of joining nodes (and the
                               next sweep evaluates marked nodes only) when the previous sweep
-                              changed fewer than alpha * W * n (node, word) pairs; 0 = 1/32 */
+                              changed fewer than alpha * W * n (node, word) pairs; 0 = 1/64 */
     int32_t profile;       /* nonzero: time the simulation kernels with HIP events (see ims_graph_profile) */
     int32_t test_flags;    /* test hooks, 0 in normal use: bit 0 = LT grid shape without a
                               threshold table (hashes drawn in the kernel); bit 1 = unused;
