@@ -1037,7 +1037,22 @@ __global__ __launch_bounds__(kBlock, 4) void ltg_sweep_kernel(SimParams P, uint3
         // trips per batch with work.
         const bool pre = !marked_only && P.W <= kRowWords;
         const uint32_t x = lane & 15u;
-        auto own_of = [&](const u32x4 d, uint64_t (&o)[2]) {
+        // a batch's in-arc source of this lane and the in-CSR offsets of its
+        // nodes 0 .. nn (low halves suffice: only differences below 2^32 are
+        // used), from clamped addresses
+        auto src_of = [&](const u32x4 d) -> uint32_t {
+            const uint32_t dtot = uniform32(d.y) >> 8;
+            const uint64_t da0 = (uint64_t)uniform32(d.z) | ((uint64_t)uniform32(d.w) << 32);
+            if (dtot == 0) return 0u;  // no in-arc to read (the batch is skipped)
+            return P.in_src32[da0 + (lane < dtot && dtot <= 64 ? lane : 0u)];
+        };
+        auto offl_of = [&](const u32x4 d) -> uint32_t {
+            const uint32_t dvf = uniform32(d.x), dnn = uniform32(d.y) & 0xFFu;
+            return reinterpret_cast<const uint32_t*>(P.in_off)[2 * ((uint64_t)dvf + (lane <= dnn ? lane : dnn))];
+        };
+        // own states and, in a dense sweep over at most 16 words, the
+        // source and offsets too
+        auto own_of = [&](const u32x4 d, uint64_t (&o)[2], uint32_t& sr, uint32_t& of) {
             const uint32_t dvf = uniform32(d.x), dnn = uniform32(d.y) & 0xFFu;
             const uint32_t xc = x < P.W ? x : 0u;
 #pragma unroll
@@ -1045,6 +1060,8 @@ __global__ __launch_bounds__(kBlock, 4) void ltg_sweep_kernel(SimParams P, uint3
                 const uint32_t j = 4 * p + (lane >> 4);
                 o[p] = P.Anm[(uint64_t)(dvf + (j < dnn ? j : 0u)) * W + xc];
             }
+            sr = src_of(d);
+            of = offl_of(d);
         };
         auto mark_of = [&](const u32x4 d) -> uint32_t {
             const uint32_t dvf = uniform32(d.x), dnn = uniform32(d.y) & 0xFFu;
@@ -1052,21 +1069,21 @@ __global__ __launch_bounds__(kBlock, 4) void ltg_sweep_kernel(SimParams P, uint3
         };
         u32x4 dA = {0, 0, 0, 0}, dB = {0, 0, 0, 0};
         uint64_t oA[2] = {0, 0};
-        uint32_t mA = 0;
+        uint32_t mA = 0, sA = 0, fA = 0;
         if (gwave < P.nbatch) {
             dA = P.bdesc[gwave];
-            if (pre) own_of(dA, oA);
+            if (pre) own_of(dA, oA, sA, fA);
             if (marked_only) mA = mark_of(dA);
         }
         if (gwave + nwaves < P.nbatch) dB = P.bdesc[gwave + nwaves];
         for (uint64_t bi = gwave; bi < P.nbatch; bi += nwaves) {
             const u32x4 dcur = dA;
             const uint64_t oc0 = oA[0], oc1 = oA[1];
-            const uint32_t mc = mA;
+            const uint32_t mc = mA, sc = sA, fc = fA;
             dA = dB;
             if (bi + 2 * nwaves < P.nbatch) dB = P.bdesc[bi + 2 * nwaves];
             if (bi + nwaves < P.nbatch) {
-                if (pre) own_of(dA, oA);
+                if (pre) own_of(dA, oA, sA, fA);
                 if (marked_only) mA = mark_of(dA);
             }
             const uint32_t vf = uniform32(dcur.x);
@@ -1117,11 +1134,8 @@ __global__ __launch_bounds__(kBlock, 4) void ltg_sweep_kernel(SimParams P, uint3
                     pending();
                     if (passes == 0) continue;
                 }
-                // this lane's in-arc source and the in-CSR offsets of nodes
-                // 0 .. nn (low halves suffice: only differences below 2^32
-                // are used)
-                const uint32_t src = P.in_src32[arc0 + (lane < total ? lane : 0u)];
-                const uint32_t offl = reinterpret_cast<const uint32_t*>(P.in_off)[2 * ((uint64_t)vf + (lane <= nn ? lane : nn))];
+                const uint32_t src = pre ? sc : src_of(dcur);
+                const uint32_t offl = pre ? fc : offl_of(dcur);
                 // complemented threshold planes: 64 bytes from the lane's
                 // first plane (the table is padded so this stays inside it);
                 // planes beyond the table's stride are those of a zero bit.
