@@ -633,7 +633,9 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
                 IMS_HIP(hipGetLastError());
             } else if (lt_mode == 2) {
                 P.kplanes = (const uint64_t*)g->thp.p;
-                hipLaunchKernelGGL(imsim::ltg_kmin_kernel, dim3(lt_blocks(imsim::ltg_kmin_kernel)), dim3(imsim::kBlock), 0, s, P,
+                // (16 workgroups per compute unit measured 1% faster per call
+                // than the resident grid for this ALU-bound kernel)
+                hipLaunchKernelGGL(imsim::ltg_kmin_kernel, dim3(fixed ? blocks : (uint32_t)g->cus * 16), dim3(imsim::kBlock), 0, s, P,
                                    (uint64_t*)g->thp.p);
                 IMS_HIP(hipGetLastError());
             }
