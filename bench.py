@@ -226,7 +226,7 @@ def main() -> int:
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": None if traffic is None else traffic["bytes_per_launch"],
-                    "kernel": "ims_simulate call (ltg_sweep_kernel sweeps, threshold table, reductions)", "kernel_ms": round(kernel_avg_s * 1e3, 4),
+                    "kernel": "ims_simulate call (count-threshold table, ltg_sweep_kernel sweeps, final pass)", "kernel_ms": round(kernel_avg_s * 1e3, 4),
                     "alg_bytes_per_launch": alg["bytes"], "alg_units_per_launch": alg["units"]}
 
     cpu = None
