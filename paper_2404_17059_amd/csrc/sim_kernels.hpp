@@ -1026,15 +1026,14 @@ __global__ __launch_bounds__(kBlock, 4) void ltg_sweep_kernel(SimParams P, uint3
         }
     };
     if (kMode == 2) {
-        // count thresholds, bit-sliced.  Batch descriptors come two batches
-        // ahead, and what decides whether a batch has work comes one batch
-        // ahead: in a dense sweep over at most 16 words the own states of its
-        // nodes, in a marked sweep their marks.  So a batch starts knowing its
-        // pending trials (dense) and only lanes with pending trials load
-        // threshold planes.  The loads that depend only on the descriptor
-        // (node offsets, in-arc sources, planes) are issued before any is
-        // waited on, and the source rows follow: two dependent memory round
-        // trips per batch with work.
+        // count thresholds, bit-sliced.  In a dense sweep batch descriptors
+        // come two batches ahead and, over at most 16 words, the own states,
+        // in-arc sources and node offsets one batch ahead, so a batch starts
+        // knowing its pending trials and only lanes with pending trials load
+        // threshold planes.  A marked sweep finds its batches 64 at a time.
+        // The loads that depend only on the descriptor (node offsets, in-arc
+        // sources, planes) are issued before any is waited on, and the source
+        // rows follow: two dependent memory round trips per batch with work.
         const bool pre = !marked_only && P.W <= kRowWords;
         const uint32_t x = lane & 15u;
         // a batch's in-arc source of this lane and the in-CSR offsets of its
@@ -1063,36 +1062,15 @@ __global__ __launch_bounds__(kBlock, 4) void ltg_sweep_kernel(SimParams P, uint3
             sr = src_of(d);
             of = offl_of(d);
         };
-        auto mark_of = [&](const u32x4 d) -> uint32_t {
-            const uint32_t dvf = uniform32(d.x), dnn = uniform32(d.y) & 0xFFu;
-            return P.nmark[(uint64_t)dvf + (lane < dnn ? lane : 0u)];
-        };
-        u32x4 dA = {0, 0, 0, 0}, dB = {0, 0, 0, 0};
-        uint64_t oA[2] = {0, 0};
-        uint32_t mA = 0, sA = 0, fA = 0;
-        if (gwave < P.nbatch) {
-            dA = P.bdesc[gwave];
-            if (pre) own_of(dA, oA, sA, fA);
-            if (marked_only) mA = mark_of(dA);
-        }
-        if (gwave + nwaves < P.nbatch) dB = P.bdesc[gwave + nwaves];
-        for (uint64_t bi = gwave; bi < P.nbatch; bi += nwaves) {
-            const u32x4 dcur = dA;
-            const uint64_t oc0 = oA[0], oc1 = oA[1];
-            const uint32_t mc = mA, sc = sA, fc = fA;
-            dA = dB;
-            if (bi + 2 * nwaves < P.nbatch) dB = P.bdesc[bi + 2 * nwaves];
-            if (bi + nwaves < P.nbatch) {
-                if (pre) own_of(dA, oA, sA, fA);
-                if (marked_only) mA = mark_of(dA);
-            }
+        // one batch: descriptor, and (dense sweeps over at most 16 words) its
+        // prefetched own states, in-arc source and node offsets
+        auto process = [&](const u32x4 dcur, const uint64_t oc0, const uint64_t oc1, const uint32_t sc, const uint32_t fc) {
             const uint32_t vf = uniform32(dcur.x);
             const uint32_t nn = uniform32(dcur.y) & 0xFFu;
             const uint32_t total = uniform32(dcur.y) >> 8;
             const uint64_t arc0 = (uint64_t)uniform32(dcur.z) | ((uint64_t)uniform32(dcur.w) << 32);
-            if (total == 0) continue;  // no in-weight: these nodes never join
-            if (total > 64) continue;  // a long row: the kMode 3 launch
-            if (marked_only && __ballot(lane < nn && mc >= min_mark) == 0) continue;
+            if (total == 0) return;  // no in-weight: these nodes never join
+            if (total > 64) return;  // a long row: the kMode 3 launch
             for (uint32_t wg = 0; wg < P.W; wg += kRowWords) {
                 const uint32_t gw = P.W - wg < kRowWords ? P.W - wg : kRowWords;
                 const uint64_t G = (W + kRowWords - 1) / kRowWords;
@@ -1253,6 +1231,50 @@ __global__ __launch_bounds__(kBlock, 4) void ltg_sweep_kernel(SimParams P, uint3
                     }
                 }
                 __builtin_amdgcn_wave_barrier();
+            }
+        };
+        if (marked_only) {
+            // a marked sweep: a wavefront scans 64 of its batches at once
+            // (lane = batch; the batches of a dense sweep's wavefront, so the
+            // work stays balanced) for a node stamped for this sweep and
+            // evaluates only those batches
+            for (uint64_t k0 = 0; gwave + k0 * nwaves < P.nbatch; k0 += 64) {
+                const uint64_t b = gwave + (k0 + lane) * nwaves;
+                u32x4 d = {0, 0, 0, 0};
+                if (b < P.nbatch) d = P.bdesc[b];
+                const uint32_t bnn = d.y & 0xFFu, btot = d.y >> 8;
+                bool hit = false;
+                if (btot >= 1 && btot <= 64)
+                    for (uint32_t j = 0; j < bnn; ++j) hit = hit || P.nmark[(uint64_t)d.x + j] >= min_mark;
+                uint64_t m = __ballot(hit);
+                while (m) {
+                    const int bit = (int)__builtin_ctzll(m);
+                    m &= m - 1;
+                    u32x4 dc;
+                    dc.x = (uint32_t)__builtin_amdgcn_readlane((int)d.x, bit);
+                    dc.y = (uint32_t)__builtin_amdgcn_readlane((int)d.y, bit);
+                    dc.z = (uint32_t)__builtin_amdgcn_readlane((int)d.z, bit);
+                    dc.w = (uint32_t)__builtin_amdgcn_readlane((int)d.w, bit);
+                    process(dc, 0, 0, 0, 0);
+                }
+            }
+        } else {
+            u32x4 dA = {0, 0, 0, 0}, dB = {0, 0, 0, 0};
+            uint64_t oA[2] = {0, 0};
+            uint32_t sA = 0, fA = 0;
+            if (gwave < P.nbatch) {
+                dA = P.bdesc[gwave];
+                if (pre) own_of(dA, oA, sA, fA);
+            }
+            if (gwave + nwaves < P.nbatch) dB = P.bdesc[gwave + nwaves];
+            for (uint64_t bi = gwave; bi < P.nbatch; bi += nwaves) {
+                const u32x4 dcur = dA;
+                const uint64_t oc0 = oA[0], oc1 = oA[1];
+                const uint32_t sc = sA, fc = fA;
+                dA = dB;
+                if (bi + 2 * nwaves < P.nbatch) dB = P.bdesc[bi + 2 * nwaves];
+                if (pre && bi + nwaves < P.nbatch) own_of(dA, oA, sA, fA);
+                process(dcur, oc0, oc1, sc, fc);
             }
         }
     } else if (kMode == 3) {
