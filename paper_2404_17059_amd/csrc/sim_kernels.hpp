@@ -1034,7 +1034,8 @@ __global__ __launch_bounds__(kBlock, 4) void ltg_sweep_kernel(SimParams P, uint3
         // The loads that depend only on the descriptor (node offsets, in-arc
         // sources, planes) are issued before any is waited on, and the source
         // rows follow: two dependent memory round trips per batch with work.
-        const bool pre = !marked_only && P.W <= kRowWords;
+        // over at most 16 words, a batch's first loads come one batch ahead
+        const bool pre = P.W <= kRowWords;
         const uint32_t x = lane & 15u;
         // a batch's in-arc source of this lane and the in-CSR offsets of its
         // nodes 0 .. nn (low halves suffice: only differences below 2^32 are
@@ -1049,22 +1050,27 @@ __global__ __launch_bounds__(kBlock, 4) void ltg_sweep_kernel(SimParams P, uint3
             const uint32_t dvf = uniform32(d.x), dnn = uniform32(d.y) & 0xFFu;
             return reinterpret_cast<const uint32_t*>(P.in_off)[2 * ((uint64_t)dvf + (lane <= dnn ? lane : dnn))];
         };
-        // own states and, in a dense sweep over at most 16 words, the
-        // source and offsets too
-        auto own_of = [&](const u32x4 d, uint64_t (&o)[2], uint32_t& sr, uint32_t& of) {
+        // a batch's first loads: own states (and marks in a marked sweep) of
+        // both passes, in-arc source, node offsets
+        struct First {
+            uint64_t own[2];
+            uint32_t mk[2], src, offl;
+        };
+        auto first_of = [&](const u32x4 d, First& f) {
             const uint32_t dvf = uniform32(d.x), dnn = uniform32(d.y) & 0xFFu;
             const uint32_t xc = x < P.W ? x : 0u;
 #pragma unroll
             for (uint32_t p = 0; p < 2; ++p) {
                 const uint32_t j = 4 * p + (lane >> 4);
-                o[p] = P.Anm[(uint64_t)(dvf + (j < dnn ? j : 0u)) * W + xc];
+                const uint64_t cell = (uint64_t)(dvf + (j < dnn ? j : 0u)) * W + xc;
+                f.own[p] = P.Anm[cell];
+                f.mk[p] = marked_only ? P.aux[cell] : 0u;
             }
-            sr = src_of(d);
-            of = offl_of(d);
+            f.src = src_of(d);
+            f.offl = offl_of(d);
         };
-        // one batch: descriptor, and (dense sweeps over at most 16 words) its
-        // prefetched own states, in-arc source and node offsets
-        auto process = [&](const u32x4 dcur, const uint64_t oc0, const uint64_t oc1, const uint32_t sc, const uint32_t fc) {
+        // one batch: descriptor and (over at most 16 words) its first loads
+        auto process = [&](const u32x4 dcur, const First& fc) {
             const uint32_t vf = uniform32(dcur.x);
             const uint32_t nn = uniform32(dcur.y) & 0xFFu;
             const uint32_t total = uniform32(dcur.y) >> 8;
@@ -1087,7 +1093,8 @@ __global__ __launch_bounds__(kBlock, 4) void ltg_sweep_kernel(SimParams P, uint3
                     live[p] = j < nn && x < gw;
                     const uint64_t cell = (uint64_t)(vf + (j < nn ? j : 0u)) * W + wg + xc;
                     if (pre) {
-                        own[p] = p ? oc1 : oc0;
+                        own[p] = fc.own[p];
+                        mk[p] = fc.mk[p];
                     } else {
                         own[p] = P.Anm[cell];
                         if (marked_only) mk[p] = P.aux[cell];
@@ -1112,8 +1119,8 @@ __global__ __launch_bounds__(kBlock, 4) void ltg_sweep_kernel(SimParams P, uint3
                     pending();
                     if (passes == 0) continue;
                 }
-                const uint32_t src = pre ? sc : src_of(dcur);
-                const uint32_t offl = pre ? fc : offl_of(dcur);
+                const uint32_t src = pre ? fc.src : src_of(dcur);
+                const uint32_t offl = pre ? fc.offl : offl_of(dcur);
                 // complemented threshold planes: 64 bytes from the lane's
                 // first plane (the table is padded so this stays inside it);
                 // planes beyond the table's stride are those of a zero bit.
@@ -1247,34 +1254,50 @@ __global__ __launch_bounds__(kBlock, 4) void ltg_sweep_kernel(SimParams P, uint3
                 if (btot >= 1 && btot <= 64)
                     for (uint32_t j = 0; j < bnn; ++j) hit = hit || P.nmark[(uint64_t)d.x + j] >= min_mark;
                 uint64_t m = __ballot(hit);
-                while (m) {
-                    const int bit = (int)__builtin_ctzll(m);
-                    m &= m - 1;
+                auto desc_at = [&](int bit) -> u32x4 {
                     u32x4 dc;
                     dc.x = (uint32_t)__builtin_amdgcn_readlane((int)d.x, bit);
                     dc.y = (uint32_t)__builtin_amdgcn_readlane((int)d.y, bit);
                     dc.z = (uint32_t)__builtin_amdgcn_readlane((int)d.z, bit);
                     dc.w = (uint32_t)__builtin_amdgcn_readlane((int)d.w, bit);
-                    process(dc, 0, 0, 0, 0);
+                    return dc;
+                };
+                // the next hit's first loads are issued before this one runs
+                First fA = {};
+                u32x4 dA = {0, 0, 0, 0};
+                if (m) {
+                    dA = desc_at((int)__builtin_ctzll(m));
+                    m &= m - 1;
+                    if (pre) first_of(dA, fA);
+                }
+                while (true) {
+                    const u32x4 dc = dA;
+                    const First fc = fA;
+                    const bool last = m == 0;
+                    if (!last) {
+                        dA = desc_at((int)__builtin_ctzll(m));
+                        m &= m - 1;
+                        if (pre) first_of(dA, fA);
+                    }
+                    process(dc, fc);
+                    if (last) break;
                 }
             }
         } else {
             u32x4 dA = {0, 0, 0, 0}, dB = {0, 0, 0, 0};
-            uint64_t oA[2] = {0, 0};
-            uint32_t sA = 0, fA = 0;
+            First fA = {};
             if (gwave < P.nbatch) {
                 dA = P.bdesc[gwave];
-                if (pre) own_of(dA, oA, sA, fA);
+                if (pre) first_of(dA, fA);
             }
             if (gwave + nwaves < P.nbatch) dB = P.bdesc[gwave + nwaves];
             for (uint64_t bi = gwave; bi < P.nbatch; bi += nwaves) {
                 const u32x4 dcur = dA;
-                const uint64_t oc0 = oA[0], oc1 = oA[1];
-                const uint32_t sc = sA, fc = fA;
+                const First fc = fA;
                 dA = dB;
                 if (bi + 2 * nwaves < P.nbatch) dB = P.bdesc[bi + 2 * nwaves];
-                if (pre && bi + nwaves < P.nbatch) own_of(dA, oA, sA, fA);
-                process(dcur, oc0, oc1, sc, fc);
+                if (pre && bi + nwaves < P.nbatch) first_of(dA, fA);
+                process(dcur, fc);
             }
         }
     } else if (kMode == 3) {
