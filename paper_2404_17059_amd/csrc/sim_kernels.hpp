@@ -1223,15 +1223,21 @@ __global__ __launch_bounds__(kBlock, 4) void ltg_sweep_kernel(SimParams P, uint3
                     if (dec) atomic_or64(&P.Anm[v * W + wg + x], dec);
                     changed += (uint32_t)__popcll(db);
                     if (marks_now) {
-                        uint64_t mb = db;
-                        while (mb) {
-                            const uint32_t bit = (uint32_t)__builtin_ctzll(mb);
-                            mb &= mb - 1;
-                            const uint64_t vm = (uint64_t)vf + 4 * p + (bit >> 4);
-                            const uint32_t w = wg + (bit & 15u);
+                        // node by node: one pass over its out-arcs stamps
+                        // every word it changed in
+#pragma unroll
+                        for (uint32_t i = 0; i < 4; ++i) {
+                            const uint32_t mw = (uint32_t)(db >> (16 * i)) & 0xFFFFu;
+                            if (mw == 0) continue;
+                            const uint64_t vm = (uint64_t)vf + 4 * p + i;
                             for (int64_t e = P.off[vm] + lane; e < P.off[vm + 1]; e += 64) {
                                 const uint64_t t = P.idx[e];
-                                P.aux[t * W + w] = sw + 2;
+                                uint32_t m = mw;
+                                while (m) {
+                                    const uint32_t xw = (uint32_t)__builtin_ctz(m);
+                                    m &= m - 1;
+                                    P.aux[t * W + wg + xw] = sw + 2;
+                                }
                                 P.nmark[t] = sw + 2;
                             }
                         }
