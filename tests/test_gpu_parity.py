@@ -213,6 +213,23 @@ def test_lt_grid_count_thresholds_with_long_rows(ims, alpha):
     run_both(ims, "lt", g.n, g.offsets, g.indices, param, seeds, 300, 31, opts=opts)
 
 
+@pytest.mark.parametrize("T,alpha", [(1000, 0.0), (1000, 1.0), (64, 1.0)])
+def test_lt_grid_trailing_nodes_without_in_arcs(ims, T, alpha):
+    """Count-threshold sweeps on a graph whose last 300 of 2,000 nodes have
+    no in-arcs, so the last batches hold no in-arc piece and start at the
+    end of the in-CSR; marking off, and always on (every sweep after the
+    first evaluates stamped batches only)."""
+    rng = np.random.default_rng(41)
+    n, m = 2000, 16000
+    g = synth.from_arcs(n, rng.integers(0, n, m), rng.integers(0, 1700, m))
+    indeg = np.bincount(g.indices, minlength=n)
+    assert indeg[1700:].sum() == 0 and indeg[:1700].sum() == g.m
+    param = synth.weighted_cascade(g)
+    seeds = np.array([3, 1750, 1999, 421], np.uint32)
+    opts = ims.Opts(shape=2, blocks_per_cu=0, alpha=alpha, profile=0, test_flags=0)
+    run_both(ims, "lt", g.n, g.offsets, g.indices, param, seeds, T, 43, opts=opts)
+
+
 @pytest.mark.parametrize("model", ["ic", "lt"])
 def test_sets_equal_single_runs_and_oracle(ims, model):
     """Many seed sets at once (common random numbers) == each set alone."""
