@@ -122,18 +122,20 @@ int ims_simulate(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_t
                  uint64_t rng_seed, const ims_opts* opts, uint32_t* trial_counts,
                  uint32_t* node_counts, uint64_t* total, uint64_t* active_bits, void* stream);
 
-/* IC only: the simulation of ims_simulate plus, per trial, the number of
- * nodes first activated at each level (paper Section 4, "Visualizations": the
- * mean number of active nodes over time).  Level 0 holds the seeds; level l
- * the nodes whose shortest live-arc path from the seed set has l arcs, the
- * synchronous step at which the cascade activates them (Section 2).
+/* The simulation of ims_simulate plus, per trial, the number of nodes first
+ * activated at each level (paper Section 4, "Visualizations": the mean number
+ * of active nodes over time).  Level 0 holds the seeds; level l the nodes the
+ * synchronous step l of Section 2 activates: for IC the nodes whose shortest
+ * live-arc path from the seed set has l arcs, for LT the nodes whose active
+ * in-weight after step l - 1 first exceeds their threshold (LT runs
+ * synchronous steps here, not the in-place sweeps of ims_simulate; the final
+ * state is the same).
  *   max_levels    >= 1; levels >= max_levels are not counted.
  *   level_counts  device uint32[max_levels * n_trials]: level_counts[l * T + t].
  *   trial_counts, total as ims_simulate.
  * Runs the word-local shape.  ims_graph_last_status() then gives the number
  * of levels processed: the deepest nonempty level is at most that number, so
- * a caller that sees it >= max_levels can retry with a larger buffer.
- * IMS_E_UNSUPPORTED for LT graphs (their grid sweeps are not synchronous). */
+ * a caller that sees it >= max_levels can retry with a larger buffer. */
 int ims_simulate_levels(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_t n_trials, uint64_t rng_seed,
                         uint32_t max_levels, uint32_t* level_counts, uint32_t* trial_counts, uint64_t* total,
                         void* stream);

@@ -216,9 +216,10 @@ def simulate(graph: Graph, seeds, n_trials: int, rng_seed: int, want_bits: bool 
 
 
 def simulate_levels(graph: Graph, seeds, n_trials: int, rng_seed: int, max_levels: int = 256, stream=None) -> dict:
-    """IC: per-trial counts of nodes first activated at each level
-    (level 0 = seeds); returns host arrays level_counts [levels, T] (trimmed
-    to the levels reached), trial_counts, and the mean spread."""
+    """Per-trial counts of nodes first activated at each level (level 0 =
+    seeds; LT runs synchronous steps here); returns host arrays level_counts
+    [levels, T] (trimmed to the levels reached), trial_counts, and the mean
+    spread."""
     torch = _torch()
     dev = torch.device("cuda", torch.cuda.current_device())
     seeds = np.ascontiguousarray(seeds, dtype=np.uint32)

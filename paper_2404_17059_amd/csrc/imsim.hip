@@ -435,7 +435,7 @@ uint32_t resident_blocks(K kernel, uint32_t cus)
     return (uint32_t)per_cu * cus;
 }
 
-// One simulation; with level_counts the word-local IC shape also counts the
+// One simulation; with level_counts the word-local shape also counts the
 // nodes first activated at every level of every trial.
 int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_t n_trials, uint64_t rng_seed,
                   const ims_opts* opts, uint32_t* trial_counts, uint32_t* node_counts, uint64_t* total, uint64_t* active_bits,
@@ -466,7 +466,7 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
     // 16 words on graphs of 1,000 to 1,000,000 nodes)
     int shape = opts ? opts->shape : 0;
     if (shape == 0) shape = W >= (uint32_t)g->cus / 4 ? 1 : 2;
-    if (level_counts) shape = 1;  // levels are the word-local IC steps
+    if (level_counts) shape = 1;  // levels are the word-local (synchronous) steps
     if (shape != 1 && shape != 2) return fail(IMS_E_INVALID_ARG, "ims_simulate: unknown shape %d", shape);
 
     if (!active_bits && (rc = ensure_buf(g, g->A, cells * 8, false))) return rc;
@@ -480,6 +480,8 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
             if ((rc = ensure_buf(g, g->aux, cells * 4, true))) return rc;
             for (int i = 0; i < 3; ++i)
                 if ((rc = ensure_buf(g, g->Q[i], cells * 4, false))) return rc;
+            // synchronous steps (level counts) hold each step's joins here
+            if (level_counts && (rc = ensure_buf(g, g->N[0], cells * 8, true))) return rc;
         }
     } else if (g->model == IMS_MODEL_IC) {
         const uint64_t qcap = (uint64_t)W * std::max<uint64_t>(g->total_chunks, 1);
@@ -738,8 +740,6 @@ int ims_simulate_levels(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, u
                         uint32_t max_levels, uint32_t* level_counts, uint32_t* trial_counts, uint64_t* total, void* stream)
 {
     if (!g) return fail(IMS_E_INVALID_ARG, "ims_simulate_levels: NULL graph");
-    if (g->model != IMS_MODEL_IC)
-        return fail(IMS_E_UNSUPPORTED, "ims_simulate_levels: IC only (LT here runs in-place sweeps, not synchronous levels)");
     if (!level_counts || max_levels == 0) return fail(IMS_E_INVALID_ARG, "ims_simulate_levels: level_counts and max_levels >= 1 required");
     if (n_trials > 0 && (uint64_t)max_levels * n_trials > 0xFFFFFFFFull)
         return fail(IMS_E_UNSUPPORTED, "ims_simulate_levels: max_levels * n_trials above 2^32");

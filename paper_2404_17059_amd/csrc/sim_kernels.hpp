@@ -101,7 +101,7 @@ struct SimParams {
     uint32_t* aux;      // word-local: per-word scratch (stamps / queue masks)
     uint32_t* nmark;    // LT grid shape: per node, the largest sweep mark of any of its words
     const uint64_t* base;  // sets form: word-major state [W][n] the sets start from, or null
-    uint32_t* level_counts;  // word-local IC: [max_levels][T] nodes first active at each level, or null
+    uint32_t* level_counts;  // word-local: [max_levels][T] nodes first active at each level (LT then runs synchronous steps), or null
     uint32_t max_levels;
     const uint32_t* seeds;
     uint32_t n_seeds;
@@ -318,7 +318,7 @@ __device__ __forceinline__ void lt_decide(const SimParams& P, uint32_t w, uint32
 // trial.
 __device__ __forceinline__ void lt_eval8_core(const SimParams& P, uint64_t* Aw, const uint64_t* Bw, uint32_t w, uint32_t lane,
                                               uint64_t myv, uint64_t pl, int64_t kb, uint32_t dg, uint64_t joined[8],
-                                              ArcStage* stage)
+                                              ArcStage* stage, uint64_t* defer)
 {
     const uint64_t n = (uint64_t)P.n;
     if (lane >= 8) {
@@ -441,10 +441,15 @@ __device__ __forceinline__ void lt_eval8_core(const SimParams& P, uint64_t* Aw, 
 
     uint64_t dec[8];
     lt_decide(P, w, lane, vsu, pend, acc, hpre, dec);
+    // joins go into the state at once (in-place steps), or, for synchronous
+    // steps, into `defer` until the step ends
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         if (dec[j] == 0) continue;
-        if (lane == 0) atomic_or64(&Aw[vsu[j]], dec[j]);
+        if (lane == 0) {
+            if (defer) defer[vsu[j]] = dec[j];
+            else atomic_or64(&Aw[vsu[j]], dec[j]);
+        }
         joined[j] = dec[j];
     }
 }
@@ -456,7 +461,8 @@ __device__ __forceinline__ void lt_eval8_core(const SimParams& P, uint64_t* Aw, 
 // is node j, joined[j] its new trials, first[j] set when it had no bit in Aw
 // before and joined now.
 __device__ __forceinline__ void lt_eval8(const SimParams& P, uint64_t* Aw, const uint64_t* Bw, uint32_t w, uint64_t myv,
-                                         uint32_t lane, uint64_t ids[8], uint64_t joined[8], bool first[8], ArcStage* stage)
+                                         uint32_t lane, uint64_t ids[8], uint64_t joined[8], bool first[8], ArcStage* stage,
+                                         uint64_t* defer)
 {
     const uint64_t n = (uint64_t)P.n;
     const uint64_t vm = valid_mask(w, P.W, P.T);
@@ -468,7 +474,7 @@ __device__ __forceinline__ void lt_eval8(const SimParams& P, uint64_t* Aw, const
     const uint64_t pl = okv ? (vm & ~(av | (Bw ? Bw[myv] : 0ull))) : 0ull;
     const int64_t kb = pl ? P.in_off[myv] : 0;
     const uint32_t dg = pl ? (uint32_t)(P.in_off[myv + 1] - kb) : 0u;
-    lt_eval8_core(P, Aw, Bw, w, lane, myv, pl, kb, dg, joined, stage);
+    lt_eval8_core(P, Aw, Bw, w, lane, myv, pl, kb, dg, joined, stage, defer);
     const uint64_t was_empty = __ballot(okv && av == 0);
 #pragma unroll
     for (int j = 0; j < 8; ++j) first[j] = joined[j] != 0 && ((was_empty >> j) & 1ull);
@@ -1487,21 +1493,31 @@ __device__ __forceinline__ uint32_t lt_task(const SimParams& P, const TaskCtx& c
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t w = c.w;
     const uint64_t vm = valid_mask(w, P.W, P.T);
+    // with level counts the steps are synchronous: every candidate of a step
+    // sees the state the step started from, and the joins (held in Nw) land
+    // at the step's end, so step l activates exactly the nodes of level l
+    const bool levels = P.level_counts != nullptr;
     if (threadIdx.x == 0) {
         sh.cnt[0] = 0;
         sh.cnt[1] = 0;
         sh.act = 0;
     }
+    if (levels && threadIdx.x < 64) sh.lvl[threadIdx.x] = 0;
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < c.n_seeds; i += kTaskBlock) {
         const uint32_t sd = c.seeds[i];
         const uint64_t nb = vm & ~(c.Bw ? c.Bw[sd] : 0ull);  // trials the seed newly activates
         if (nb == 0) continue;
         c.Aw[sd] = nb;
+        if (levels) count_level_bits(sh, nb);
         c.L[0][atomicAdd(&sh.cnt[0], 1u)] = sd;
         if (c.act) c.act[atomicAdd(&sh.act, 1u)] = sd;
     }
     __syncthreads();
+    if (levels) {
+        flush_level(P, sh, w, 0);
+        __syncthreads();
+    }
     uint32_t cur = 0, steps = 0;
     for (;;) {
         const uint32_t cnt = sh.cnt[cur];
@@ -1547,7 +1563,7 @@ __device__ __forceinline__ uint32_t lt_task(const SimParams& P, const TaskCtx& c
             uint64_t vs[8], joined[8];
             bool first[8];
             const uint64_t mine = (lane < 8 && it + lane < ncand) ? (uint64_t)c.C[it + lane] : ~0ull;
-            lt_eval8(P, c.Aw, c.Bw, w, mine, lane, vs, joined, first, sh.stage[threadIdx.x >> 6]);
+            lt_eval8(P, c.Aw, c.Bw, w, mine, lane, vs, joined, first, sh.stage[threadIdx.x >> 6], levels ? c.Nw : nullptr);
 #pragma unroll
             for (int j = 0; j < 8; ++j)
                 if (joined[j] && lane == 0) {
@@ -1556,6 +1572,20 @@ __device__ __forceinline__ uint32_t lt_task(const SimParams& P, const TaskCtx& c
                 }
         }
         __syncthreads();
+        if (levels) {
+            // the step's joins land together; each joined node is listed once
+            const uint32_t nj = sh.cnt[nxt];
+            for (uint32_t i = threadIdx.x; i < nj; i += kTaskBlock) {
+                const uint32_t v = (nxt ? c.L[1] : c.L[0])[i];
+                const uint64_t d = c.Nw[v];
+                c.Aw[v] |= d;
+                c.Nw[v] = 0;
+                count_level_bits(sh, d);
+            }
+            __syncthreads();
+            flush_level(P, sh, w, steps);
+            __syncthreads();
+        }
         cur = nxt;
     }
     __syncthreads();
@@ -1649,7 +1679,7 @@ __global__ __launch_bounds__(kTaskBlock, 2) void word_kernel(SimParams P, uint64
             c.stamp = nullptr;
             c.stamp_base = 0;
         } else {
-            c.Nw = nullptr;
+            c.Nw = (!kSets && P.level_counts) ? P.N[0] + slot * n : nullptr;
             c.M[0] = c.M[1] = nullptr;
             c.C = (uint32_t*)P.Q[2] + slot * list_cap;
             c.stamp = (kSets ? P.sstamp : P.aux) + slot * n;

@@ -136,6 +136,31 @@ def lt_fixpoint(n: int, src, dst, w64, seeds, h) -> set:
     return act
 
 
+def lt_sync_levels(n: int, src, dst, w64, seeds, h) -> list:
+    """Synchronous LT steps for fixed threshold hashes h[v] (Section 2: a node
+    joins at step s when the in-weight of the nodes active after step s - 1
+    exceeds its threshold): the step at which each node joins, 0 for the
+    seeds, -1 for nodes that never join."""
+    level = [-1] * n
+    for s in seeds:
+        level[int(s)] = 0
+    step = 0
+    while True:
+        step += 1
+        joins = []
+        for v in range(n):
+            if level[v] >= 0:
+                continue
+            tot = sum(int(w64[e]) for e in range(len(src))
+                      if int(dst[e]) == v and 0 <= level[int(src[e])] < step)
+            if tot > h[v]:
+                joins.append(v)
+        if not joins:
+            return level
+        for v in joins:
+            level[v] = step
+
+
 def brute_lt_thresholds(n: int, src, dst, w64, seeds):
     """Exact LT spread by enumerating, per node, the intervals of its 32-bit
     threshold hash between consecutive distinct subset sums of its in-weights

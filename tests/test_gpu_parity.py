@@ -303,12 +303,42 @@ def test_ic_level_counts_match_oracle_levels(ims, case):
     assert short["truncated"] == (got["levels_processed"] + 1 > 3)
 
 
-def test_level_counts_reject_lt(ims):
-    g = synth.barabasi_albert(500, 3, seed=24)
-    G = ims.Graph(g.n, g.offsets, g.indices, "lt", synth.weighted_cascade(g))
-    with pytest.raises(ims.ImsError) as e:
-        ims.simulate_levels(G, np.array([1], np.uint32), 64, 1)
-    assert e.value.code == -8
+@pytest.mark.parametrize("case", ["random", "ba_hubs"])
+def test_lt_level_counts_match_oracle_levels(ims, case):
+    """LT with level counts runs synchronous steps: per-trial counts of nodes
+    first active at each step equal the histogram of the oracle's levels,
+    and the final state equals the oracle's (the in-place runs reach the same
+    fixpoint).  ba_hubs has nodes with more than 64 in-arcs."""
+    if case == "random":
+        rng = np.random.default_rng(37)
+        n = 800
+        off, idx = pins.csr_from_arcs(n, rng.integers(0, n, size=4000), rng.integers(0, n, size=4000))
+        indeg = np.bincount(idx, minlength=n)
+        param = rng.choice([1.0, 0.7], size=n)[idx] / np.maximum(indeg[idx], 1)
+        seeds, T, rs = np.array([4, 9, 100, 701], np.uint32), 200, 61
+    else:
+        g = synth.barabasi_albert(3000, 4, seed=38)
+        n, off, idx = g.n, g.offsets, g.indices
+        param = synth.weighted_cascade(g)
+        seeds, T, rs = synth.random_seeds(n, 6, seed=39), 130, 62
+    say(f"[parity] lt levels case={case} n={n} T={T}")
+    G = ims.Graph(n, off, idx, "lt", param)
+    got = ims.simulate_levels(G, seeds, T, rs, max_levels=512)
+    assert not got["truncated"]
+    enc = oracle.encode("lt", param)
+    r = oracle.simulate("lt", n, off, idx, enc, seeds, T, rs, want_levels=True, threads=8)
+    L = got["level_counts"].shape[0]
+    deepest = int(r["levels"].max())
+    assert deepest >= 3
+    expect = np.zeros((max(L, deepest + 1), T), dtype=np.int64)
+    for t in range(T):
+        lv = r["levels"][t]
+        expect[:, t] = np.bincount(lv[lv >= 0], minlength=expect.shape[0])
+    np.testing.assert_array_equal(got["level_counts"].astype(np.int64), expect[:L])
+    assert expect[L:].sum() == 0
+    np.testing.assert_array_equal(got["trial_counts"], r["trial_counts"])
+    assert got["total"] == r["total"]
+    G.close()
 
 
 @pytest.mark.parametrize("model,shape", [("ic", 0), ("lt", 0), ("lt", 2)])

@@ -164,6 +164,31 @@ def test_lt_sets_equal_least_fixpoint(gseed):
         assert sets[t] == expect, t
 
 
+@pytest.mark.parametrize("gseed", [0, 1])
+def test_lt_levels_equal_synchronous_steps(gseed):
+    """The oracle's LT activation levels are the synchronous steps of Section
+    2, recomputed here step by step from the weights and the threshold
+    hashes (numpy Philox)."""
+    rng = np.random.default_rng(60 + gseed)
+    n = 30
+    src, dst = random_digraph(n, 110, rng, self_loops=True)
+    off, idx = pins.csr_from_arcs(n, src, dst)
+    indeg = np.bincount(idx, minlength=n)
+    frac = rng.choice([1.0, 0.6, 0.9], size=n)
+    w64 = oracle.encode_w(frac[idx] / indeg[idx])
+    seeds = np.array([2, 17], dtype=np.uint32)
+    T, rs = 40, 90 + gseed
+    r = oracle.simulate("lt", n, off, idx, w64, seeds, T, rs, want_levels=True)
+    h = pins.numpy_hash32_table(rs, 2, T, n)
+    arc_src = np.repeat(np.arange(n), np.diff(off))
+    deepest = 0
+    for t in range(T):
+        expect = pins.lt_sync_levels(n, arc_src, idx, w64, seeds, [int(x) for x in h[t]])
+        np.testing.assert_array_equal(r["levels"][t], np.array(expect, dtype=np.int32))
+        deepest = max(deepest, max(expect))
+    assert deepest >= 3  # the cases reach several steps
+
+
 def test_ic_coin_comparison_is_strict():
     # one arc 0 -> 1; the coin of (trial 0, arc 0) decides
     off = np.array([0, 1, 1], dtype=np.int64)
