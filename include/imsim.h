@@ -93,8 +93,9 @@ int ims_graph_info(const ims_graph* g, int64_t* n, int64_t* m, int* model);
 
 /* Simulation options; NULL = automatic.  Any setting gives the same bits. */
 typedef struct ims_opts {
-    int shape;             /* 0 = auto (word-local when the run has at least a quarter as many
-                              64-trial words as compute units, else grid-wide), 1 = word-local
+    int shape;             /* 0 = auto (IC: word-local when the run has at least a quarter as
+                              many 64-trial words as compute units, else grid-wide; LT: grid-
+                              wide), 1 = word-local
                               (one workgroup per 64-trial word runs its whole cascade), 2 = grid-
                               wide steps (one launch per level / sweep) */
     int32_t blocks_per_cu; /* workgroups per compute unit; 0 = auto */
