@@ -439,7 +439,7 @@ uint32_t resident_blocks(K kernel, uint32_t cus)
 // nodes first activated at every level of every trial.
 int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_t n_trials, uint64_t rng_seed,
                   const ims_opts* opts, uint32_t* trial_counts, uint32_t* node_counts, uint64_t* total, uint64_t* active_bits,
-                  void* stream, uint32_t* level_counts, uint32_t max_levels)
+                  void* stream, uint32_t* level_counts, uint32_t max_levels, uint32_t w0 = 0, bool accumulate = false)
 {
     if (!g) return fail(IMS_E_INVALID_ARG, "ims_simulate: NULL graph");
     if (n_trials == 0) return fail(IMS_E_INVALID_ARG, "ims_simulate: n_trials must be >= 1");
@@ -473,6 +473,22 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
     if (shape == 0) shape = g->model == IMS_MODEL_LT ? 2 : (W >= (uint32_t)g->cus / 4 ? 1 : 2);
     if (level_counts) shape = 1;  // levels are the word-local (synchronous) steps
     if (shape != 1 && shape != 2) return fail(IMS_E_INVALID_ARG, "ims_simulate: unknown shape %d", shape);
+    // LT grid shape over more than 16 words: runs of 16 words one after the
+    // other (trials are independent; each run hashes its trials by their
+    // global index), so every run takes the sweep's 16-word form; per-node
+    // counts and the total accumulate over the runs
+    if (shape == 2 && g->model == IMS_MODEL_LT && W > imsim::kRowWords && w0 == 0 && !accumulate) {
+        ims_opts o = opts ? *opts : ims_opts{};
+        o.shape = 2;
+        for (uint32_t c0 = 0; c0 < W; c0 += imsim::kRowWords) {
+            const uint32_t tc = std::min<uint32_t>(imsim::kRowWords * 64u, n_trials - 64u * c0);
+            rc = simulate_impl(g, seeds, n_seeds, tc, rng_seed, &o, trial_counts + 64ull * c0, node_counts, total,
+                               active_bits ? active_bits + (uint64_t)c0 * (uint64_t)g->n : nullptr, stream, nullptr, 0, c0,
+                               c0 > 0);
+            if (rc) return rc;
+        }
+        return IMS_OK;
+    }
 
     if (!active_bits && (rc = ensure_buf(g, g->A, cells * 8, false))) return rc;
     if (shape == 1) {
@@ -539,9 +555,10 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
         if (g->aux.p && (rc = fill_async<uint8_t>((uint8_t*)g->aux.p, g->aux.bytes, 0, s))) return rc;
         g->zero_dirty = false;
     }
-    if ((rc = fill_async<uint32_t>(g->d_status, 4, 0u, s))) return rc;
+    // (a later 16-word run keeps an earlier run's guard flag)
+    if (!accumulate && (rc = fill_async<uint32_t>(g->d_status, 4, 0u, s))) return rc;
     if ((rc = fill_async<uint32_t>(trial_counts, n_trials, 0u, s))) return rc;
-    if ((rc = fill_async<unsigned long long>((unsigned long long*)total, 1, 0ull, s))) return rc;
+    if (!accumulate && (rc = fill_async<unsigned long long>((unsigned long long*)total, 1, 0ull, s))) return rc;
 
     imsim::SimParams P;
     P.n = g->n;
@@ -577,6 +594,7 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
     P.nmark = (uint32_t*)g->nmark.p;
     P.base = nullptr;
     P.level_counts = level_counts;
+    P.w0 = w0;
     P.max_levels = max_levels;
     P.seeds = g->d_seeds;
     P.n_seeds = (uint32_t)sv.size();
@@ -707,7 +725,7 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
         if (g->model == IMS_MODEL_LT && cells > 0) {
             hipLaunchKernelGGL(imsim::ltg_finish_kernel, dim3((uint32_t)std::min<uint64_t>(g->cus, ((uint64_t)g->n + 255) / 256)),
                                dim3(imsim::kBlock), 0, s, (const uint64_t*)P.Anm, active_bits, g->n, W, n_trials, trial_counts,
-                               node_counts, (unsigned long long*)total);
+                               node_counts, (unsigned long long*)total, accumulate ? 1 : 0);
             IMS_HIP(hipGetLastError());
         }
     }

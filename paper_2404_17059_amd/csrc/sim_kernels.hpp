@@ -103,6 +103,7 @@ struct SimParams {
     const uint64_t* base;  // sets form: word-major state [W][n] the sets start from, or null
     uint32_t* level_counts;  // word-local: [max_levels][T] nodes first active at each level (LT then runs synchronous steps), or null
     uint32_t max_levels;
+    uint32_t w0;  // LT grid shape: global index of word 0 of this run (runs of at most 16 words)
     const uint32_t* seeds;
     uint32_t n_seeds;
     uint64_t seed_arcs;  // out-arcs of the seeds (predicts the first sweep's changes)
@@ -672,7 +673,7 @@ __global__ __launch_bounds__(kBlock) void ltg_table_kernel(SimParams P, uint32_t
         const uint64_t v = (it / W) * 8 + (lane >> 3);
         const uint32_t g = lane & 7;
         if (v >= n) continue;
-        const Block4 b = philox_block(v, (uint64_t)w * 8 + g, P.seed, kDomainLtNode);
+        const Block4 b = philox_block(v, ((uint64_t)P.w0 + w) * 8 + g, P.seed, kDomainLtNode);
         uint4* dst = reinterpret_cast<uint4*>(th32 + (v * W + w) * 64 + 8 * g);
         dst[0] = make_uint4((uint32_t)b.w0, (uint32_t)(b.w0 >> 32), (uint32_t)b.w1, (uint32_t)(b.w1 >> 32));
         dst[1] = make_uint4((uint32_t)b.w2, (uint32_t)(b.w2 >> 32), (uint32_t)b.w3, (uint32_t)(b.w3 >> 32));
@@ -731,7 +732,7 @@ __global__ __launch_bounds__(kBlock) void ltg_kmin_kernel(SimParams P, uint64_t*
                 const uint32_t w = (uint32_t)grp * kRowWords + h8 + x;
                 uint32_t k[8];
                 if (v < n && w < W) {
-                    const Block4 b = philox_block(v, (uint64_t)w * 8 + q, P.seed, kDomainLtNode);
+                    const Block4 b = philox_block(v, ((uint64_t)P.w0 + w) * 8 + q, P.seed, kDomainLtNode);
 #pragma unroll
                     for (uint32_t i = 0; i < 8; ++i) k[i] = kmin_of(block_lane(b, i), wv, inv, kmax);
                 } else {
@@ -1012,7 +1013,7 @@ __global__ __launch_bounds__(kBlock, 4) void ltg_sweep_kernel(SimParams P, uint3
                     // this lane's trial: join when the in-weight exceeds its hash
                     uint32_t h = h_tab;
                     if (kMode != 1) {
-                        const Block4 blk = philox_block(v, (uint64_t)w * 8 + (lane >> 3), P.seed, kDomainLtNode);
+                        const Block4 blk = philox_block(v, ((uint64_t)P.w0 + w) * 8 + (lane >> 3), P.seed, kDomainLtNode);
                         h = block_lane(blk, lane & 7);
                     }
                     const bool join = acc > (uint64_t)h;
@@ -1777,7 +1778,8 @@ __global__ __launch_bounds__(kTaskBlock, 2) void batch_kernel(const BatchItem* _
 // before one atomic add per (block, trial).
 __global__ __launch_bounds__(kBlock) void ltg_finish_kernel(const uint64_t* __restrict__ Anm, uint64_t* __restrict__ A, int64_t n,
                                                           uint32_t W, uint32_t T, uint32_t* __restrict__ trial_counts,
-                                                          uint32_t* __restrict__ node_counts, unsigned long long* __restrict__ total)
+                                                          uint32_t* __restrict__ node_counts, unsigned long long* __restrict__ total,
+                                                          int accumulate)
 {
     __shared__ uint32_t part[kWaves][kRowWords][64];
     __shared__ unsigned long long tpart[kWaves];
@@ -1816,7 +1818,7 @@ __global__ __launch_bounds__(kBlock) void ltg_finish_kernel(const uint64_t* __re
                 if (A && ok) A[(uint64_t)(wg + x) * (uint64_t)n + v] = wd[x];
                 acc[x] += (uint32_t)__popcll(wave_transpose64(wd[x], lane));
             }
-            if (ok && node_counts) node_counts[v] = (wg == 0 ? 0u : node_counts[v]) + c;
+            if (ok && node_counts) node_counts[v] = (wg == 0 && !accumulate ? 0u : node_counts[v]) + c;
             sum += c;
         }
 #pragma unroll
