@@ -100,7 +100,8 @@ struct ims_graph {
     uint32_t* d_in_src32 = nullptr;  // source per in-arc (uniform-weight form)
     uint32_t* d_node_w = nullptr;    // common weight piece per node (uniform-weight form)
     bool lt_uniform = false;
-    uint32_t kp_stride = 8;          // planes per (node, word) of the count-threshold table
+    uint32_t* d_kinfo = nullptr;     // per node: low half of its in-CSR offset, first plane in the count table
+    uint64_t kplanes_total = 0;      // count-table planes per word summed over the nodes
     uint32_t* d_bfirst = nullptr;    // LT grid shape: first node of each batch
     uint32_t* d_bdesc = nullptr;     // LT grid shape: 4 words per batch (see SimParams::bdesc)
     uint32_t* d_bigb = nullptr;      // LT grid shape: batches with more than 64 in-arc pieces
@@ -157,6 +158,7 @@ struct ims_graph {
         dev_free(d_node_w);
         dev_free(d_bfirst);
         dev_free(d_bdesc);
+        dev_free(d_kinfo);
         dev_free(d_bigb);
         dev_free(d_qcount);
         dev_free(d_seeds);
@@ -327,17 +329,31 @@ int ims_graph_create(int64_t n, int64_t m, const int64_t* offsets, const uint32_
                 else if (piece != node_w[v]) { uniform = false; break; }
             }
         g->lt_uniform = uniform;
-        // count-threshold planes: an even count S with 2^S - 1 above every
-        // count a node with at most 64 in-arc pieces can reach
-        {
-            int64_t dmax = 0;
-            for (int64_t v = 0; v < n; ++v) {
+        // count-threshold planes per node: the fewest S with 2^S - 1 above
+        // every count the node can reach (its in-arc pieces, at most 64 for
+        // the nodes that use the table; 0 planes for the others, 1 for a node
+        // without in-arcs)
+        // (the first plane is kept in 32 bits: a table within its memory
+        // budget has fewer than 2^32 planes per word)
+        if (uniform) {
+            std::vector<uint32_t> kinfo(2 * ((size_t)n + 1), 0);
+            uint64_t planes_total = 0;
+            for (int64_t v = 0; v <= n; ++v) {
+                kinfo[2 * v] = (uint32_t)in_off[v];
+                kinfo[2 * v + 1] = (uint32_t)planes_total;
+                if (v == n) break;
                 const int64_t d = in_off[v + 1] - in_off[v];
-                if (d <= 64 && d > dmax) dmax = d;
+                uint32_t planes = 0;
+                if (d <= 64) {
+                    planes = 1;
+                    while (((1ll << planes) - 1) <= d) ++planes;
+                }
+                planes_total += planes;
             }
-            uint32_t planes = 2;
-            while (planes < 8 && ((1ll << planes) - 1) <= dmax) planes += 2;
-            g->kp_stride = planes;
+            g->kplanes_total = planes_total;
+            if ((rc = dev_alloc(&g->d_kinfo, kinfo.size()))) return bail(rc);
+            if (hipMemcpy(g->d_kinfo, kinfo.data(), sizeof(uint32_t) * kinfo.size(), hipMemcpyHostToDevice) != hipSuccess)
+                return bail(fail(IMS_E_HIP, "in-CSR upload failed"));
         }
         if (uniform) {
             for (int64_t k = 0; k < mi; ++k) src32[k] = (uint32_t)in_arc[k];
@@ -521,10 +537,11 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
     // per plane and node-word, words padded to whole groups), full hashes
     // (256 B), or hashes drawn in the kernel
     int lt_mode = 0;
-    const uint64_t kmin_bytes =
-        (uint64_t)g->n * ((W + imsim::kRowWords - 1) / imsim::kRowWords) * imsim::kRowWords * 8ull * g->kp_stride;
+    const uint64_t kmin_bytes = g->kplanes_total * ((W + imsim::kRowWords - 1) / imsim::kRowWords) * imsim::kRowWords * 8ull;
     if (shape == 2 && g->model == IMS_MODEL_LT && !(test_flags & 1)) {
-        if (g->lt_uniform && !(test_flags & 4) && kmin_bytes <= kThresholdTableBudget && !(test_flags & 8)) lt_mode = 2;
+        if (g->lt_uniform && !(test_flags & 4) && kmin_bytes <= kThresholdTableBudget && g->kplanes_total < (1ull << 32) &&
+            !(test_flags & 8))
+            lt_mode = 2;
         else if (cells * 256 <= kThresholdTableBudget) lt_mode = 1;
     }
     const bool use_table = lt_mode != 0;
@@ -576,7 +593,7 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
     P.thp = nullptr;
     P.th32 = nullptr;
     P.kplanes = nullptr;
-    P.kp_stride = g->kp_stride;
+    P.kinfo = g->d_kinfo;
     P.thp_shift = (test_flags & 2) ? 31u : 16u;
     P.A = A;
     P.Anm = (uint64_t*)g->Anm.p;

@@ -49,6 +49,7 @@ constexpr uint32_t kRowWords = 16;   // LT grid shape: words of a source row sta
 constexpr uint32_t kRowPitch = 17;   // LT grid shape: LDS row pitch in uint64 (odd: spreads banks)
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4a8 __attribute__((ext_vector_type(4), aligned(8)));  // 8-byte aligned
 
 struct SimParams {
     int64_t n;
@@ -76,12 +77,13 @@ struct SimParams {
     const uint32_t* __restrict__ th32;
     // LT grid shape, equal in-weights: per (node, trial) the least number of
     // active in-arc pieces that makes the node join, k = floor(h / w_v) + 1,
-    // saturated at 2^S - 1 (at most 127) with S = kp_stride, stored as
-    // complemented bit planes: uint64 ((v*G + g)*16 + x)*S + b
-    // (G = ceil(W / 16)) holds NOT bit b of k for the 64 trials of word
-    // 16g + x (or null)
+    // saturated at 2^S_v - 1 (at most 127) with S_v planes for node v
+    // (S_v = F(v+1) - F(v), F(v) = kinfo[2v + 1]), stored as complemented bit
+    // planes: uint64 16*G*F(v) + (16g + x)*S_v + b (G = ceil(W / 16)) holds
+    // NOT bit b of k for the 64 trials of word 16g + x (or null).  kinfo[2v]
+    // is the low half of in_off[v]
     const uint64_t* __restrict__ kplanes;
-    uint32_t kp_stride;  // planes per (node, word) in kplanes: 2, 4, 6 or 8
+    const uint32_t* __restrict__ kinfo;
     // LT grid shape: node batches whose in-arcs fit one 64-arc chunk (or one
     // node with more); batch b holds nodes bfirst[b] .. bfirst[b+1]-1
     const uint32_t* __restrict__ bfirst;
@@ -713,8 +715,6 @@ __global__ __launch_bounds__(kBlock) void ltg_kmin_kernel(SimParams P, uint64_t*
     __shared__ uint32_t stage[kWaves][8 * kKminNodePitch];
     const uint64_t n = (uint64_t)P.n;
     const uint32_t W = P.W;
-    const uint32_t S = P.kp_stride;
-    const uint32_t kmax = S >= 7 ? 127u : (1u << S) - 1u;
     const uint64_t G = (W + kRowWords - 1) / kRowWords;
     const uint64_t items = ((n + 7) / 8) * G;
     const uint32_t lane = threadIdx.x & 63u;
@@ -727,11 +727,15 @@ __global__ __launch_bounds__(kBlock) void ltg_kmin_kernel(SimParams P, uint64_t*
         const uint64_t v = v0 + j;
         const uint32_t wv = v < n ? P.node_w[v] : 0u;
         const uint32_t inv = wv >= 2 ? (uint32_t)(0x100000000ull / wv) : 0u;
+        // this lane's node: its planes S and table block, k saturated at 2^S - 1
+        const uint64_t ko = v < n ? P.kinfo[2 * v + 1] : 0u;
+        const uint32_t S = v < n ? P.kinfo[2 * v + 3] - (uint32_t)ko : 0u;
+        const uint32_t kmax = S >= 7 ? 127u : (1u << S) - 1u;
         for (uint32_t h8 = 0; h8 < kRowWords; h8 += 8) {
             for (uint32_t x = 0; x < 8; ++x) {
                 const uint32_t w = (uint32_t)grp * kRowWords + h8 + x;
                 uint32_t k[8];
-                if (v < n && w < W) {
+                if (v < n && w < W && S > 0) {
                     const Block4 b = philox_block(v, ((uint64_t)P.w0 + w) * 8 + q, P.seed, kDomainLtNode);
 #pragma unroll
                     for (uint32_t i = 0; i < 8; ++i) k[i] = kmin_of(block_lane(b, i), wv, inv, kmax);
@@ -745,11 +749,14 @@ __global__ __launch_bounds__(kBlock) void ltg_kmin_kernel(SimParams P, uint64_t*
             __builtin_amdgcn_wave_barrier();
             for (uint32_t jj = 0; jj < 8; ++jj) {
                 if (v0 + jj >= n) break;
+                const uint32_t Sj = uniform32(__shfl(S, (int)(8 * jj)));
+                if (Sj == 0) continue;  // a long row: no table
+                const uint64_t kj = uniform64(__shfl(ko, (int)(8 * jj)));
                 const uint32_t* src = St + jj * kKminNodePitch + 3 * lane;
                 const uint64_t r = wave_transpose64((uint64_t)src[0] | ((uint64_t)src[1] << 32), lane);
                 // lane 8x + b: plane b of word h8 + x
-                if ((lane & 7u) < S)
-                    kplanes[(((v0 + jj) * G + grp) * kRowWords + h8 + (lane >> 3)) * S + (lane & 7u)] = ~r;
+                if ((lane & 7u) < Sj)
+                    kplanes[kj * kRowWords * G + (grp * kRowWords + h8 + (lane >> 3)) * Sj + (lane & 7u)] = ~r;
             }
             __builtin_amdgcn_wave_barrier();
         }
@@ -1053,15 +1060,17 @@ __global__ __launch_bounds__(kBlock, 4) void ltg_sweep_kernel(SimParams P, uint3
             if (dtot == 0) return 0u;  // no in-arc to read (the batch is skipped)
             return P.in_src32[da0 + (lane < dtot && dtot <= 64 ? lane : 0u)];
         };
-        auto offl_of = [&](const u32x4 d) -> uint32_t {
+        // ... and, of the same nodes, the first threshold plane
+        auto info_of = [&](const u32x4 d) -> uint2 {
             const uint32_t dvf = uniform32(d.x), dnn = uniform32(d.y) & 0xFFu;
-            return reinterpret_cast<const uint32_t*>(P.in_off)[2 * ((uint64_t)dvf + (lane <= dnn ? lane : dnn))];
+            return reinterpret_cast<const uint2*>(P.kinfo)[(uint64_t)dvf + (lane <= dnn ? lane : dnn)];
         };
         // a batch's first loads: own states (and marks in a marked sweep) of
-        // both passes, in-arc source, node offsets
+        // both passes, in-arc source, node offsets and first planes
         struct First {
             uint64_t own[2];
-            uint32_t mk[2], src, offl;
+            uint32_t mk[2], src;
+            uint2 info;
         };
         auto first_of = [&](const u32x4 d, First& f) {
             const uint32_t dvf = uniform32(d.x), dnn = uniform32(d.y) & 0xFFu;
@@ -1074,7 +1083,7 @@ __global__ __launch_bounds__(kBlock, 4) void ltg_sweep_kernel(SimParams P, uint3
                 f.mk[p] = marked_only ? P.aux[cell] : 0u;
             }
             f.src = src_of(d);
-            f.offl = offl_of(d);
+            f.info = info_of(d);
         };
         // one batch: descriptor and (over at most 16 words) its first loads
         auto process = [&](const u32x4 dcur, const First& fc) {
@@ -1127,26 +1136,29 @@ __global__ __launch_bounds__(kBlock, 4) void ltg_sweep_kernel(SimParams P, uint3
                     if (passes == 0) continue;
                 }
                 const uint32_t src = pre ? fc.src : src_of(dcur);
-                const uint32_t offl = pre ? fc.offl : offl_of(dcur);
+                const uint2 info = pre ? fc.info : info_of(dcur);
+                const uint32_t offl = info.x;
                 // complemented threshold planes: 64 bytes from the lane's
                 // first plane (the table is padded so this stays inside it);
-                // planes beyond the table's stride are those of a zero bit.
+                // planes beyond the node's S are those of a zero bit.
                 // (Non-temporal loads here measured 5% slower per call.)
                 auto load_planes = [&](uint32_t p, uint64_t (&k)[8]) {
 #pragma unroll
                     for (uint32_t q = 0; q < 8; ++q) k[q] = ~0ull;
-                    if (known && pq[p] == 0) return;
                     const uint32_t j = 4 * p + (lane >> 4);
-                    const u32x4* kp = reinterpret_cast<const u32x4*>(
-                        P.kplanes + (((uint64_t)(vf + (j < nn ? j : 0u)) * G + grp) * kRowWords + xc) * P.kp_stride);
+                    const uint32_t f0 = (uint32_t)__shfl((int)info.y, (int)j);
+                    const uint32_t S = (uint32_t)__shfl((int)info.y, (int)(j + 1)) - f0;
+                    if (known && pq[p] == 0) return;
+                    const u32x4a8* kp = reinterpret_cast<const u32x4a8*>(
+                        P.kplanes + (uint64_t)f0 * kRowWords * G + (grp * kRowWords + xc) * S);
 #pragma unroll
                     for (uint32_t q = 0; q < 4; ++q) {
-                        const u32x4 t = kp[q];
+                        const u32x4a8 t = kp[q];
                         k[2 * q] = (uint64_t)t.x | ((uint64_t)t.y << 32);
                         k[2 * q + 1] = (uint64_t)t.z | ((uint64_t)t.w << 32);
                     }
 #pragma unroll
-                    for (uint32_t b = 0; b < 8; ++b) k[b] = b < P.kp_stride ? k[b] : ~0ull;
+                    for (uint32_t b = 0; b < 8; ++b) k[b] = b < S ? k[b] : ~0ull;
                 };
                 uint64_t k0[8];
                 load_planes(0, k0);
