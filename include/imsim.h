@@ -198,9 +198,13 @@ typedef struct ims_batch_item {
 typedef struct ims_tuning {
     int32_t blocks_per_cu;  /* persistent workgroups per compute unit (1..16) */
     int32_t order;          /* 0 = items by estimated cost, largest first; 1 = item order */
+    int32_t split;          /* tasks per 64-trial word: 1, 2, 4, ... 64 trials per task = 64 / split
+                               (rounded down to a power of two; values below 1 mean 1).  A task runs
+                               the cascade of its trials alone, so a split shortens the longest
+                               task at the cost of more, smaller tasks; results do not change */
 } ims_tuning;
 
-/* tuning NULL = defaults (2 per CU, largest first).  Synchronous. */
+/* tuning NULL = defaults (2 per CU, largest first, 16 tasks per word).  Synchronous. */
 int ims_batch_create(const ims_batch_item* items, uint32_t n_items, const ims_tuning* tuning, ims_batch** out);
 /* Time every candidate schedule `repeats` times on `stream`, check that all
  * give identical outputs, keep the fastest (reported in *chosen if not NULL)

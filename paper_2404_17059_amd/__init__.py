@@ -45,7 +45,7 @@ class BatchItem(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("blocks_per_cu", ctypes.c_int32), ("order", ctypes.c_int32)]
+    _fields_ = [("blocks_per_cu", ctypes.c_int32), ("order", ctypes.c_int32), ("split", ctypes.c_int32)]
 
 
 def _sig(name, res, *args):
@@ -317,7 +317,7 @@ class Batch:
     persistent launch; the first launch captures a HIP graph that later
     launches replay.  items: (Graph, seeds, n_trials, rng_seed) tuples."""
 
-    def __init__(self, items, tuning: tuple[int, int] | None = None, want_node_counts: bool = True):
+    def __init__(self, items, tuning: tuple[int, int, int] | None = None, want_node_counts: bool = True):
         torch = _torch()
         dev = torch.device("cuda", torch.cuda.current_device())
         self.graphs = [it[0] for it in items]
@@ -340,10 +340,11 @@ class Batch:
                "ims_batch_create")
         self._h = h
 
-    def autotune(self, repeats: int = 2, stream=None) -> tuple[int, int]:
+    def autotune(self, repeats: int = 2, stream=None) -> tuple[int, int, int]:
+        """Returns the chosen (blocks_per_cu, order, split)."""
         t = Tuning()
         _check(_lib.ims_batch_autotune(self._h, int(repeats), _stream_handle(stream), ctypes.byref(t)), "ims_batch_autotune")
-        return int(t.blocks_per_cu), int(t.order)
+        return int(t.blocks_per_cu), int(t.order), int(t.split)
 
     def launch(self, stream=None) -> None:
         _check(_lib.ims_batch_launch(self._h, _stream_handle(stream)), "ims_batch_launch")

@@ -926,12 +926,12 @@ struct ims_batch {
     std::vector<imsim::BatchItem> host_items;
     std::vector<uint32_t*> dev_seeds;
     std::vector<double> cost;
-    ims_tuning tuning{2, 0};
+    ims_tuning tuning{2, 0, 16};
     int device = 0, cus = 0;
     uint64_t max_n = 1;
     uint32_t n_tasks = 0;
     imsim::BatchItem* d_items = nullptr;
-    uint32_t* d_tasks = nullptr;
+    uint64_t* d_tasks = nullptr;
     uint32_t* d_ctl = nullptr;  // [0] task counter, [1..2] status
     ims_graph::Buf sA, sN, sQ0, sQ1, sQ2, sact, sstamp, ssteps;
     uint32_t slots = 0;
@@ -983,14 +983,25 @@ int batch_plan(ims_batch* b)
     for (uint32_t i = 0; i < n_items; ++i) order[i] = i;
     if (b->tuning.order == 0)
         std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) { return b->cost[x] > b->cost[y]; });
-    std::vector<uint32_t> tasks;
-    for (uint32_t i : order)
-        for (uint32_t w = 0; w < b->host_items[i].P.W; ++w) tasks.push_back((i << 12) | w);
+    // each word of an item as 2^s tasks of 64 / 2^s trials (s from the
+    // tuning's split); parts wholly past the item's last trial are left out
+    uint32_t s = 0;
+    while (s < 6 && (2u << s) <= (uint32_t)std::max(b->tuning.split, 1)) ++s;
+    const uint32_t width = 64u >> s;
+    std::vector<uint64_t> tasks;
+    for (uint32_t i : order) {
+        const uint32_t T = b->host_items[i].P.T;
+        for (uint32_t w = 0; w < b->host_items[i].P.W; ++w)
+            for (uint32_t part = 0; part < (1u << s); ++part)
+                if ((uint64_t)w * 64 + (uint64_t)part * width < T)
+                    tasks.push_back(((uint64_t)i << 32) | ((uint64_t)s << 24) | ((uint64_t)part << 16) | w);
+    }
+    if (tasks.size() >= 0xFFFFFFFFull) return fail(IMS_E_UNSUPPORTED, "ims_batch: more than 2^32 - 2 tasks");
     b->n_tasks = (uint32_t)tasks.size();
     dev_free(b->d_tasks);
     int rc = dev_alloc(&b->d_tasks, tasks.size());
     if (rc) return rc;
-    if (!tasks.empty()) IMS_HIP(hipMemcpy(b->d_tasks, tasks.data(), tasks.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    if (!tasks.empty()) IMS_HIP(hipMemcpy(b->d_tasks, tasks.data(), tasks.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
     const int per_cu = std::min(std::max(b->tuning.blocks_per_cu, 1), 16);
     b->slots = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(b->n_tasks, (uint64_t)b->cus * per_cu));
     const uint64_t cells = (uint64_t)b->slots * b->max_n;
@@ -1018,7 +1029,7 @@ int batch_enqueue(ims_batch* b, hipStream_t s)
     }
     if ((rc = fill_async<uint32_t>(b->d_ctl, 4, 0u, s))) return rc;
     hipLaunchKernelGGL(imsim::batch_kernel, dim3(b->slots), dim3(imsim::kTaskBlock), 0, s, (const imsim::BatchItem*)b->d_items,
-                       (const uint32_t*)b->d_tasks, b->n_tasks, b->d_ctl, b->max_n, (uint64_t*)b->sA.p, (uint64_t*)b->sN.p,
+                       (const uint64_t*)b->d_tasks, b->n_tasks, b->d_ctl, b->max_n, (uint64_t*)b->sA.p, (uint64_t*)b->sN.p,
                        (uint32_t*)b->sQ0.p, (uint32_t*)b->sQ1.p, (uint64_t*)b->sQ2.p, (uint32_t*)b->sact.p, (uint32_t*)b->sstamp.p,
                        (uint32_t*)b->ssteps.p, b->d_ctl + 1);
     IMS_HIP(hipGetLastError());
@@ -1129,7 +1140,7 @@ int ims_batch_autotune(ims_batch* b, int repeats, void* stream, ims_tuning* chos
 {
     if (!b || repeats < 1) return fail(IMS_E_INVALID_ARG, "ims_batch_autotune: bad arguments");
     hipStream_t s = (hipStream_t)stream;
-    const ims_tuning cands[] = {{1, 0}, {2, 0}, {4, 0}, {8, 0}, {2, 1}, {4, 1}};
+    const ims_tuning cands[] = {{2, 0, 1}, {2, 0, 4}, {2, 0, 16}, {4, 0, 16}, {2, 1, 16}, {2, 0, 64}, {4, 0, 64}};
     hipEvent_t e0, e1;
     IMS_HIP(hipEventCreate(&e0));
     IMS_HIP(hipEventCreate(&e1));
@@ -1152,7 +1163,7 @@ int ims_batch_autotune(ims_batch* b, int repeats, void* stream, ims_tuning* chos
             IMS_HIP(hipMemcpy(&cur[i], b->items[i].total, sizeof(uint64_t), hipMemcpyDeviceToHost));
         if (ref.empty()) ref = cur;
         else if (cur != ref) {
-            rc = fail(IMS_E_HIP, "ims_batch_autotune: schedule {%d,%d} changed the results", c.blocks_per_cu, c.order);
+            rc = fail(IMS_E_HIP, "ims_batch_autotune: schedule {%d,%d,%d} changed the results", c.blocks_per_cu, c.order, c.split);
             break;
         }
         if (ms / repeats < best_ms) {

@@ -459,16 +459,16 @@ __device__ __forceinline__ void lt_eval8_core(const SimParams& P, uint64_t* Aw, 
 
 // LT evaluation of up to 8 nodes of word w against the word's state row Aw,
 // over the read-only base row Bw when given (a node is active in a trial when
-// either has the bit; joins go to Aw only).  Lane j < 8 passes node j in
-// `myv` (ids >= n are absent; other lanes pass anything).  On return ids[j]
-// is node j, joined[j] its new trials, first[j] set when it had no bit in Aw
-// before and joined now.
-__device__ __forceinline__ void lt_eval8(const SimParams& P, uint64_t* Aw, const uint64_t* Bw, uint32_t w, uint64_t myv,
-                                         uint32_t lane, uint64_t ids[8], uint64_t joined[8], bool first[8], ArcStage* stage,
-                                         uint64_t* defer)
+// either has the bit; joins go to Aw only), in the trials of `tmask` only.
+// Lane j < 8 passes node j in `myv` (ids >= n are absent; other lanes pass
+// anything).  On return ids[j] is node j, joined[j] its new trials, first[j]
+// set when it had no bit in Aw before and joined now.
+__device__ __forceinline__ void lt_eval8(const SimParams& P, uint64_t* Aw, const uint64_t* Bw, uint32_t w, uint64_t tmask,
+                                         uint64_t myv, uint32_t lane, uint64_t ids[8], uint64_t joined[8], bool first[8],
+                                         ArcStage* stage, uint64_t* defer)
 {
     const uint64_t n = (uint64_t)P.n;
-    const uint64_t vm = valid_mask(w, P.W, P.T);
+    const uint64_t vm = valid_mask(w, P.W, P.T) & tmask;
     if (lane >= 8) myv = ~0ull;
 #pragma unroll
     for (int j = 0; j < 8; ++j) ids[j] = uniform64(__shfl(myv, j));
@@ -1370,6 +1370,7 @@ struct TaskShared {
 // Where one task keeps its state.
 struct TaskCtx {
     uint32_t w;
+    uint64_t tmask;        // the task's trials within word w (all 64 but in split batch tasks)
     uint64_t* Aw;          // active masks of the task's word
     const uint64_t* Bw;    // incremental sets form: the word's base masks (read only), else null
     uint64_t* Nw;          // IC: next-step masks (zero between steps)
@@ -1411,7 +1412,7 @@ __device__ __forceinline__ uint32_t ic_task(const SimParams& P, const TaskCtx& c
 {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t w = c.w;
-    const uint64_t vm = valid_mask(w, P.W, P.T);
+    const uint64_t vm = valid_mask(w, P.W, P.T) & c.tmask;
     const bool levels = P.level_counts != nullptr;
     if (threadIdx.x == 0) {
         sh.cnt[0] = 0;
@@ -1505,7 +1506,7 @@ __device__ __forceinline__ uint32_t lt_task(const SimParams& P, const TaskCtx& c
 {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t w = c.w;
-    const uint64_t vm = valid_mask(w, P.W, P.T);
+    const uint64_t vm = valid_mask(w, P.W, P.T) & c.tmask;
     // with level counts the steps are synchronous: every candidate of a step
     // sees the state the step started from, and the joins (held in Nw) land
     // at the step's end, so step l activates exactly the nodes of level l
@@ -1576,7 +1577,8 @@ __device__ __forceinline__ uint32_t lt_task(const SimParams& P, const TaskCtx& c
             uint64_t vs[8], joined[8];
             bool first[8];
             const uint64_t mine = (lane < 8 && it + lane < ncand) ? (uint64_t)c.C[it + lane] : ~0ull;
-            lt_eval8(P, c.Aw, c.Bw, w, mine, lane, vs, joined, first, sh.stage[threadIdx.x >> 6], levels ? c.Nw : nullptr);
+            lt_eval8(P, c.Aw, c.Bw, w, c.tmask, mine, lane, vs, joined, first, sh.stage[threadIdx.x >> 6],
+                     levels ? c.Nw : nullptr);
 #pragma unroll
             for (int j = 0; j < 8; ++j)
                 if (joined[j] && lane == 0) {
@@ -1663,6 +1665,7 @@ __global__ __launch_bounds__(kTaskBlock, 2) void word_kernel(SimParams P, uint64
         const uint32_t t = sh.task;
         if (t >= n_tasks) break;
         TaskCtx c;
+        c.tmask = ~0ull;
         uint32_t set = 0;
         uint64_t slot;
         if (kSets) {
@@ -1728,9 +1731,17 @@ struct BatchItem {
     uint64_t* total;         // [1]
 };
 
-// Batch form: tasks[t] = item << 12 | word, in the order the schedule chose.
-// Slot state rows are sized for the largest item.
-__global__ __launch_bounds__(kTaskBlock, 2) void batch_kernel(const BatchItem* __restrict__ items, const uint32_t* __restrict__ tasks,
+// Batch form: tasks[t] = item << 32 | s << 24 | part << 16 | word, in the
+// order the schedule chose: the task runs trials [part * 64 / 2^s,
+// (part + 1) * 64 / 2^s) of the word (s = 0: the whole word).  Slot state
+// rows are sized for the largest item.
+__device__ __forceinline__ uint64_t split_mask(uint32_t s, uint32_t part)
+{
+    const uint32_t width = 64u >> s;
+    return s == 0 ? ~0ull : ((1ull << width) - 1ull) << (width * part);
+}
+
+__global__ __launch_bounds__(kTaskBlock, 2) void batch_kernel(const BatchItem* __restrict__ items, const uint64_t* __restrict__ tasks,
                                                        uint32_t n_tasks, uint32_t* task_counter, uint64_t max_n,
                                                        uint64_t* sA, uint64_t* sN, uint32_t* sQ0, uint32_t* sQ1, uint64_t* sQ2,
                                                        uint32_t* sact, uint32_t* sstamp, uint32_t* slot_steps, uint32_t* status)
@@ -1745,11 +1756,12 @@ __global__ __launch_bounds__(kTaskBlock, 2) void batch_kernel(const BatchItem* _
         __syncthreads();
         const uint32_t t = sh.task;
         if (t >= n_tasks) break;
-        const uint32_t code = tasks[t];
-        const BatchItem& it = items[code >> 12];
+        const uint64_t code = tasks[t];
+        const BatchItem& it = items[code >> 32];
         const SimParams& P = it.P;
         TaskCtx c;
-        c.w = code & 0xFFFu;
+        c.w = (uint32_t)code & 0xFFFFu;
+        c.tmask = split_mask(((uint32_t)code >> 24) & 7u, ((uint32_t)code >> 16) & 63u);
         c.seeds = P.seeds;
         c.n_seeds = P.n_seeds;
         c.act = sact + slot * max_n;

@@ -454,10 +454,32 @@ def test_batch_equals_single_runs_across_graph_replays(ims):
         ref = oracle.simulate(model, g.n, g.offsets, g.indices, oracle.encode(model, param), sd, T, rs, want_bits=False)
         assert r["total"] == ref["total"]
     chosen = B.autotune(repeats=1)
-    assert chosen[0] >= 1
+    assert chosen[0] >= 1 and chosen[2] >= 1
     B.launch()
     torch.cuda.synchronize()
     assert [r["total"] for r in B.results()] == [s1["total"] for s1 in singles]
+    B.close()
+    for it in items:
+        it[0].close()
+
+
+@pytest.mark.parametrize("split", [2, 16, 64])
+def test_batch_split_tasks_equal_single_runs(ims, split):
+    """Words split into `split` tasks of 64 / split trials each (trial
+    counts with ragged last words: parts past the last trial are skipped)
+    give the per-item results of whole-word runs, over two replays."""
+    import torch
+    items, specs = _batch_items(ims)
+    singles = [ims.simulate(G, sd, T, rs) for (G, sd, T, rs) in items]
+    B = ims.Batch(items, tuning=(2, 0, split))
+    for rep in range(2):
+        say(f"[parity] batch split {split} replay {rep}")
+        B.launch()
+        torch.cuda.synchronize()
+        for k, (r, s1) in enumerate(zip(B.results(), singles)):
+            assert r["total"] == s1["total"], (rep, k)
+            assert (r["trial_counts"] == s1["trial_counts"].cpu().numpy().view(np.uint32)).all(), (rep, k)
+            assert (r["node_counts"] == s1["node_counts"].cpu().numpy().view(np.uint32)).all(), (rep, k)
     B.close()
     for it in items:
         it[0].close()
