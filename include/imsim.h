@@ -204,7 +204,7 @@ typedef struct ims_tuning {
                                task at the cost of more, smaller tasks; results do not change */
 } ims_tuning;
 
-/* tuning NULL = defaults (2 per CU, largest first, 16 tasks per word).  Synchronous. */
+/* tuning NULL = defaults (2 per CU, largest first, 8 tasks per word).  Synchronous. */
 int ims_batch_create(const ims_batch_item* items, uint32_t n_items, const ims_tuning* tuning, ims_batch** out);
 /* Time every candidate schedule `repeats` times on `stream`, check that all
  * give identical outputs, keep the fastest (reported in *chosen if not NULL)

@@ -926,7 +926,7 @@ struct ims_batch {
     std::vector<imsim::BatchItem> host_items;
     std::vector<uint32_t*> dev_seeds;
     std::vector<double> cost;
-    ims_tuning tuning{2, 0, 16};
+    ims_tuning tuning{2, 0, 8};
     int device = 0, cus = 0;
     uint64_t max_n = 1;
     uint32_t n_tasks = 0;
@@ -1140,7 +1140,7 @@ int ims_batch_autotune(ims_batch* b, int repeats, void* stream, ims_tuning* chos
 {
     if (!b || repeats < 1) return fail(IMS_E_INVALID_ARG, "ims_batch_autotune: bad arguments");
     hipStream_t s = (hipStream_t)stream;
-    const ims_tuning cands[] = {{2, 0, 1}, {2, 0, 4}, {2, 0, 16}, {4, 0, 16}, {2, 1, 16}, {2, 0, 64}, {4, 0, 64}};
+    const ims_tuning cands[] = {{2, 0, 1}, {2, 0, 4}, {2, 0, 8}, {4, 0, 8}, {2, 1, 8}, {2, 0, 16}, {2, 0, 64}};
     hipEvent_t e0, e1;
     IMS_HIP(hipEventCreate(&e0));
     IMS_HIP(hipEventCreate(&e1));

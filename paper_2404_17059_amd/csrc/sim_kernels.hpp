@@ -1371,6 +1371,7 @@ struct TaskShared {
 struct TaskCtx {
     uint32_t w;
     uint64_t tmask;        // the task's trials within word w (all 64 but in split batch tasks)
+    uint32_t group;        // the 8-trial group holding all of the task's trials, or 8 when they span more
     uint64_t* Aw;          // active masks of the task's word
     const uint64_t* Bw;    // incremental sets form: the word's base masks (read only), else null
     uint64_t* Nw;          // IC: next-step masks (zero between steps)
@@ -1404,6 +1405,12 @@ __device__ __forceinline__ void flush_level(const SimParams& P, TaskShared& sh, 
     }
 }
 
+// Narrow tasks (all trials in one 8-trial group): a lane takes a whole
+// frontier node or candidate when it has at most kNarrowDeg arcs on the side
+// walked, with every load of that walk issued before any is used; nodes with
+// more arcs go through the wavefront-wide walk.
+constexpr uint32_t kNarrowDeg = 16;
+
 // IC cascade of one task.  Per step every wavefront takes frontier entries
 // and walks their out-arcs lane-strided; a node's first new bit of the step
 // appends it to the next list (counter in LDS); after a barrier the next
@@ -1413,6 +1420,7 @@ __device__ __forceinline__ uint32_t ic_task(const SimParams& P, const TaskCtx& c
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t w = c.w;
     const uint64_t vm = valid_mask(w, P.W, P.T) & c.tmask;
+    const bool narrow = c.group < 8;
     const bool levels = P.level_counts != nullptr;
     if (threadIdx.x == 0) {
         sh.cnt[0] = 0;
@@ -1455,31 +1463,67 @@ __device__ __forceinline__ uint32_t ic_task(const SimParams& P, const TaskCtx& c
             sh.next_item = 0;
         }
         __syncthreads();
-        for (;;) {
-            uint32_t it = 0;
-            if (lane == 0) it = atomicAdd(&sh.next_item, 1u);
-            it = __shfl(it, 0);
-            if (it >= cnt) break;
-            const uint32_t u = (cur ? c.L[1] : c.L[0])[it];
-            const uint64_t mask = (cur ? c.M[1] : c.M[0])[it];
-            const int64_t e1 = P.off[u + 1];
-            for (int64_t e = P.off[u] + lane; e < e1; e += 64) {
-                const uint32_t v = P.idx[e];
-                const uint32_t th = P.thr[e];
-                if (th == 0) continue;
-                const uint64_t todo = mask & ~(c.Aw[v] | (c.Bw ? c.Bw[v] : 0ull));
-                if (todo == 0) continue;
-                const uint64_t live = ic_live(todo, th, (uint64_t)e, w, P.seed);
-                if (live == 0) continue;
-                const uint64_t old = atomic_or64(&c.Aw[v], live);
-                const uint64_t fresh = live & ~old;
-                if (levels) count_level_bits(sh, fresh);
-                if (c.act && old == 0) c.act[atomicAdd(&sh.act, 1u)] = v;
-                if (fresh == 0 || P.off[v + 1] == P.off[v]) continue;
-                if (atomic_or64(&c.Nw[v], fresh) == 0) {
-                    const uint32_t pos = atomicAdd(&sh.cnt[nxt], 1u);
-                    (nxt ? c.L[1] : c.L[0])[pos] = v;
+        // one out-arc e = (u, v) of a frontier node whose new trials are `mask`
+        auto exam = [&](int64_t e, uint32_t v, uint32_t th, uint64_t mask) {
+            if (th == 0) return;
+            const uint64_t todo = mask & ~(c.Aw[v] | (c.Bw ? c.Bw[v] : 0ull));
+            if (todo == 0) return;
+            const uint64_t live = ic_live(todo, th, (uint64_t)e, w, P.seed);
+            if (live == 0) return;
+            const uint64_t old = atomic_or64(&c.Aw[v], live);
+            const uint64_t fresh = live & ~old;
+            if (levels) count_level_bits(sh, fresh);
+            if (c.act && old == 0) c.act[atomicAdd(&sh.act, 1u)] = v;
+            if (fresh == 0 || P.off[v + 1] == P.off[v]) return;
+            if (atomic_or64(&c.Nw[v], fresh) == 0) {
+                const uint32_t pos = atomicAdd(&sh.cnt[nxt], 1u);
+                (nxt ? c.L[1] : c.L[0])[pos] = v;
+            }
+        };
+        if (narrow) {
+            // a lane per frontier node of at most kNarrowDeg out-arcs; the
+            // wavefront walks larger ones together
+            for (;;) {
+                uint32_t it = 0;
+                if (lane == 0) it = atomicAdd(&sh.next_item, 64u);
+                it = __shfl(it, 0);
+                if (it >= cnt) break;
+                const bool have = it + lane < cnt;
+                const uint32_t u = have ? (cur ? c.L[1] : c.L[0])[it + lane] : 0u;
+                const uint64_t mask = have ? (cur ? c.M[1] : c.M[0])[it + lane] : 0ull;
+                const int64_t e0 = have ? P.off[u] : 0;
+                const uint32_t deg = have ? (uint32_t)(P.off[u + 1] - e0) : 0u;
+                if (deg <= kNarrowDeg) {
+                    uint32_t vv[kNarrowDeg], tt[kNarrowDeg];
+#pragma unroll
+                    for (uint32_t i = 0; i < kNarrowDeg; ++i) {
+                        vv[i] = i < deg ? P.idx[e0 + i] : 0u;
+                        tt[i] = i < deg ? P.thr[e0 + i] : 0u;
+                    }
+#pragma unroll
+                    for (uint32_t i = 0; i < kNarrowDeg; ++i)
+                        if (i < deg) exam(e0 + i, vv[i], tt[i], mask);
                 }
+                uint64_t big = __ballot(deg > kNarrowDeg);
+                while (big) {
+                    const int j = __builtin_ctzll(big);
+                    big &= big - 1;
+                    const uint32_t ub = uniform32(__shfl(u, j));
+                    const uint64_t mb = uniform64(__shfl(mask, j));
+                    const int64_t e1 = P.off[ub + 1];
+                    for (int64_t e = P.off[ub] + lane; e < e1; e += 64) exam(e, P.idx[e], P.thr[e], mb);
+                }
+            }
+        } else {
+            for (;;) {
+                uint32_t it = 0;
+                if (lane == 0) it = atomicAdd(&sh.next_item, 1u);
+                it = __shfl(it, 0);
+                if (it >= cnt) break;
+                const uint32_t u = (cur ? c.L[1] : c.L[0])[it];
+                const uint64_t mask = (cur ? c.M[1] : c.M[0])[it];
+                const int64_t e1 = P.off[u + 1];
+                for (int64_t e = P.off[u] + lane; e < e1; e += 64) exam(e, P.idx[e], P.thr[e], mask);
             }
         }
         __syncthreads();
@@ -1497,6 +1541,65 @@ __device__ __forceinline__ uint32_t ic_task(const SimParams& P, const TaskCtx& c
     return steps;
 }
 
+
+// byte j of the result = bit j of a (a < 256)
+__device__ __forceinline__ uint64_t spread8(uint32_t a)
+{
+    uint64_t s = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < 8; ++j) s |= (uint64_t)((a >> j) & 1u) << (8 * j);
+    return s;
+}
+
+// LT decision for candidate v of a narrow task (trials 8g .. 8g + 7 of word
+// w), pending trials `pend`, in-arc pieces k0 .. k0 + dg - 1 (dg <=
+// kNarrowDeg), evaluated by one lane: the active in-weight of each pending
+// trial against its threshold hash.  Returns the trials in which v joins.
+__device__ __forceinline__ uint64_t lt_eval_lane(const SimParams& P, const uint64_t* Aw, const uint64_t* Bw, uint32_t w, uint32_t g,
+                                                 uint64_t v, uint64_t pend, int64_t k0, uint32_t dg)
+{
+    const uint32_t sh = 8 * g;
+    const uint32_t p8 = (uint32_t)(pend >> sh) & 0xFFu;
+    uint64_t acc[8];
+    if (P.lt_uniform) {
+        // equal in-weights: count active sources per trial (bytes of `packed`)
+        uint32_t src[kNarrowDeg];
+#pragma unroll
+        for (uint32_t i = 0; i < kNarrowDeg; ++i) src[i] = i < dg ? P.in_src32[k0 + i] : 0u;
+        uint64_t packed = 0;
+#pragma unroll
+        for (uint32_t i = 0; i < kNarrowDeg; ++i)
+            if (i < dg) {
+                const uint64_t a = load_relaxed(&Aw[src[i]]) | (Bw ? Bw[src[i]] : 0ull);
+                packed += spread8((uint32_t)(a >> sh) & p8);
+            }
+        const uint64_t wv = P.node_w[v];
+#pragma unroll
+        for (uint32_t j = 0; j < 8; ++j) acc[j] = ((packed >> (8 * j)) & 0xFFull) * wv;
+    } else {
+        uint64_t arc[kNarrowDeg];
+#pragma unroll
+        for (uint32_t i = 0; i < kNarrowDeg; ++i) arc[i] = i < dg ? P.in_arc[k0 + i] : 0ull;
+#pragma unroll
+        for (uint32_t j = 0; j < 8; ++j) acc[j] = 0;
+#pragma unroll
+        for (uint32_t i = 0; i < kNarrowDeg; ++i)
+            if (i < dg) {
+                const uint32_t s32 = (uint32_t)arc[i];
+                const uint64_t a = load_relaxed(&Aw[s32]) | (Bw ? Bw[s32] : 0ull);
+                const uint32_t a8 = (uint32_t)(a >> sh) & p8;
+                const uint64_t wt = arc[i] >> 32;
+#pragma unroll
+                for (uint32_t j = 0; j < 8; ++j) acc[j] += ((a8 >> j) & 1u) ? wt : 0ull;
+            }
+    }
+    const Block4 b = philox_block(v, (uint64_t)w * 8 + g, P.seed, kDomainLtNode);
+    uint32_t d8 = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < 8; ++j) d8 |= (((p8 >> j) & 1u) && acc[j] > (uint64_t)block_lane(b, j)) ? 1u << j : 0u;
+    return (uint64_t)d8 << sh;
+}
+
 // LT cascade of one task.  The frontier list holds the nodes that joined in
 // the previous step (any trial); their out-neighbours with an inactive trial
 // are collected once each into a candidate list (stamp_base + step marks the
@@ -1507,6 +1610,7 @@ __device__ __forceinline__ uint32_t lt_task(const SimParams& P, const TaskCtx& c
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t w = c.w;
     const uint64_t vm = valid_mask(w, P.W, P.T) & c.tmask;
+    const bool narrow = c.group < 8;
     // with level counts the steps are synchronous: every candidate of a step
     // sees the state the step started from, and the joins (held in Nw) land
     // at the step's end, so step l activates exactly the nodes of level l
@@ -1551,32 +1655,59 @@ __device__ __forceinline__ uint32_t lt_task(const SimParams& P, const TaskCtx& c
         }
         __syncthreads();
         // push side: out-neighbours of the frontier with an inactive trial
-        for (;;) {
-            uint32_t it = 0;
-            if (lane == 0) it = atomicAdd(&sh.next_item, 1u);
-            it = __shfl(it, 0);
-            if (it >= cnt) break;
-            const uint32_t u = (cur ? c.L[1] : c.L[0])[it];
-            const int64_t e1 = P.off[u + 1];
-            for (int64_t e = P.off[u] + lane; e < e1; e += 64) {
-                const uint32_t v = P.idx[e];
-                if ((vm & ~(c.Aw[v] | (c.Bw ? c.Bw[v] : 0ull))) == 0) continue;
-                if (atomicMax(&c.stamp[v], mark) < mark) c.C[atomicAdd(&sh.cand, 1u)] = v;
+        auto collect = [&](uint32_t v) {
+            if ((vm & ~(c.Aw[v] | (c.Bw ? c.Bw[v] : 0ull))) == 0) return;
+            if (atomicMax(&c.stamp[v], mark) < mark) c.C[atomicAdd(&sh.cand, 1u)] = v;
+        };
+        if (narrow) {
+            // a lane per frontier node of at most kNarrowDeg out-arcs
+            for (;;) {
+                uint32_t it = 0;
+                if (lane == 0) it = atomicAdd(&sh.next_item, 64u);
+                it = __shfl(it, 0);
+                if (it >= cnt) break;
+                const bool have = it + lane < cnt;
+                const uint32_t u = have ? (cur ? c.L[1] : c.L[0])[it + lane] : 0u;
+                const int64_t e0 = have ? P.off[u] : 0;
+                const uint32_t deg = have ? (uint32_t)(P.off[u + 1] - e0) : 0u;
+                if (deg <= kNarrowDeg) {
+                    uint32_t vv[kNarrowDeg];
+#pragma unroll
+                    for (uint32_t i = 0; i < kNarrowDeg; ++i) vv[i] = i < deg ? P.idx[e0 + i] : 0u;
+#pragma unroll
+                    for (uint32_t i = 0; i < kNarrowDeg; ++i)
+                        if (i < deg) collect(vv[i]);
+                }
+                uint64_t big = __ballot(deg > kNarrowDeg);
+                while (big) {
+                    const int j = __builtin_ctzll(big);
+                    big &= big - 1;
+                    const uint32_t ub = uniform32(__shfl(u, j));
+                    const int64_t e1 = P.off[ub + 1];
+                    for (int64_t e = P.off[ub] + lane; e < e1; e += 64) collect(P.idx[e]);
+                }
+            }
+        } else {
+            for (;;) {
+                uint32_t it = 0;
+                if (lane == 0) it = atomicAdd(&sh.next_item, 1u);
+                it = __shfl(it, 0);
+                if (it >= cnt) break;
+                const uint32_t u = (cur ? c.L[1] : c.L[0])[it];
+                const int64_t e1 = P.off[u + 1];
+                for (int64_t e = P.off[u] + lane; e < e1; e += 64) collect(P.idx[e]);
             }
         }
         __syncthreads();
         if (threadIdx.x == 0) sh.next_item = 0;
         __syncthreads();
-        // pull side: evaluate candidates eight at a time
+        // pull side: evaluate candidates eight at a time (narrow tasks: a lane
+        // per candidate of at most kNarrowDeg in-arc pieces, the others eight
+        // at a time)
         const uint32_t ncand = sh.cand;
-        for (;;) {
-            uint32_t it = 0;
-            if (lane == 0) it = atomicAdd(&sh.next_item, 8u);
-            it = __shfl(it, 0);
-            if (it >= ncand) break;
+        auto eval8 = [&](uint64_t mine) {
             uint64_t vs[8], joined[8];
             bool first[8];
-            const uint64_t mine = (lane < 8 && it + lane < ncand) ? (uint64_t)c.C[it + lane] : ~0ull;
             lt_eval8(P, c.Aw, c.Bw, w, c.tmask, mine, lane, vs, joined, first, sh.stage[threadIdx.x >> 6],
                      levels ? c.Nw : nullptr);
 #pragma unroll
@@ -1585,6 +1716,49 @@ __device__ __forceinline__ uint32_t lt_task(const SimParams& P, const TaskCtx& c
                     (nxt ? c.L[1] : c.L[0])[atomicAdd(&sh.cnt[nxt], 1u)] = (uint32_t)vs[j];
                     if (c.act && first[j]) c.act[atomicAdd(&sh.act, 1u)] = (uint32_t)vs[j];
                 }
+        };
+        if (narrow) {
+            for (;;) {
+                uint32_t it = 0;
+                if (lane == 0) it = atomicAdd(&sh.next_item, 64u);
+                it = __shfl(it, 0);
+                if (it >= ncand) break;
+                const bool have = it + lane < ncand;
+                const uint32_t v = have ? c.C[it + lane] : 0u;
+                const uint64_t av = have ? load_relaxed(&c.Aw[v]) : 0ull;
+                const uint64_t pend = have ? vm & ~(av | (c.Bw ? c.Bw[v] : 0ull)) : 0ull;
+                const int64_t k0 = pend ? P.in_off[v] : 0;
+                const uint32_t dg = pend ? (uint32_t)(P.in_off[v + 1] - k0) : 0u;
+                const bool small = pend != 0 && dg <= kNarrowDeg;
+                const uint64_t dec = small ? lt_eval_lane(P, c.Aw, c.Bw, w, c.group, v, pend, k0, dg) : 0ull;
+                if (dec) {
+                    if (levels) c.Nw[v] = dec;
+                    else atomic_or64(&c.Aw[v], dec);
+                    (nxt ? c.L[1] : c.L[0])[atomicAdd(&sh.cnt[nxt], 1u)] = v;
+                    if (c.act && av == 0) c.act[atomicAdd(&sh.act, 1u)] = v;
+                }
+                uint64_t wide = __ballot(pend != 0 && !small);
+                while (wide) {
+                    uint64_t mine = ~0ull;
+#pragma unroll
+                    for (uint32_t q = 0; q < 8; ++q) {
+                        if (!wide) break;
+                        const int j = __builtin_ctzll(wide);
+                        wide &= wide - 1;
+                        const uint32_t vj = uniform32(__shfl(v, j));
+                        if (lane == q) mine = vj;
+                    }
+                    eval8(mine);
+                }
+            }
+        } else {
+            for (;;) {
+                uint32_t it = 0;
+                if (lane == 0) it = atomicAdd(&sh.next_item, 8u);
+                it = __shfl(it, 0);
+                if (it >= ncand) break;
+                eval8((lane < 8 && it + lane < ncand) ? (uint64_t)c.C[it + lane] : ~0ull);
+            }
         }
         __syncthreads();
         if (levels) {
@@ -1666,6 +1840,7 @@ __global__ __launch_bounds__(kTaskBlock, 2) void word_kernel(SimParams P, uint64
         if (t >= n_tasks) break;
         TaskCtx c;
         c.tmask = ~0ull;
+        c.group = 8;
         uint32_t set = 0;
         uint64_t slot;
         if (kSets) {
@@ -1741,7 +1916,7 @@ __device__ __forceinline__ uint64_t split_mask(uint32_t s, uint32_t part)
     return s == 0 ? ~0ull : ((1ull << width) - 1ull) << (width * part);
 }
 
-__global__ __launch_bounds__(kTaskBlock, 2) void batch_kernel(const BatchItem* __restrict__ items, const uint64_t* __restrict__ tasks,
+__global__ __launch_bounds__(kTaskBlock, 4) void batch_kernel(const BatchItem* __restrict__ items, const uint64_t* __restrict__ tasks,
                                                        uint32_t n_tasks, uint32_t* task_counter, uint64_t max_n,
                                                        uint64_t* sA, uint64_t* sN, uint32_t* sQ0, uint32_t* sQ1, uint64_t* sQ2,
                                                        uint32_t* sact, uint32_t* sstamp, uint32_t* slot_steps, uint32_t* status)
@@ -1761,7 +1936,11 @@ __global__ __launch_bounds__(kTaskBlock, 2) void batch_kernel(const BatchItem* _
         const SimParams& P = it.P;
         TaskCtx c;
         c.w = (uint32_t)code & 0xFFFFu;
-        c.tmask = split_mask(((uint32_t)code >> 24) & 7u, ((uint32_t)code >> 16) & 63u);
+        {
+            const uint32_t sp = ((uint32_t)code >> 24) & 7u, part = ((uint32_t)code >> 16) & 63u;
+            c.tmask = split_mask(sp, part);
+            c.group = sp >= 3 ? (part << (6 - sp)) >> 3 : 8u;
+        }
         c.seeds = P.seeds;
         c.n_seeds = P.n_seeds;
         c.act = sact + slot * max_n;

@@ -416,7 +416,9 @@ def test_celf_equals_greedy_and_oracle_greedy(ims):
     G.close()
 
 
-def _batch_items(ims, count=10, seed=3):
+def _batch_items(ims, count=10, seed=3, unequal_lt=False):
+    """Uneven IC/LT items; with unequal_lt every other LT item gets random
+    in-weights (sums 0.9 per node) instead of 1/indeg."""
     rng = np.random.default_rng(seed)
     items, specs = [], []
     for i in range(count):
@@ -424,6 +426,10 @@ def _batch_items(ims, count=10, seed=3):
         g = synth.erdos_renyi_directed(n, 6.0, 50 + i) if i % 2 == 0 else synth.barabasi_albert(n, 3, 50 + i)
         model = "ic" if (i // 2) % 2 == 0 else "lt"
         param = synth.weighted_cascade(g)
+        if unequal_lt and model == "lt" and i % 4 == 3:
+            u = rng.uniform(0.05, 1.0, size=g.m)
+            insum = np.bincount(g.indices, weights=u, minlength=g.n)
+            param = 0.9 * u / insum[g.indices]
         seeds = synth.random_seeds(n, int(rng.integers(0, 12)), 70 + i)
         T = int(rng.choice([1, 64, 100, 190]))
         G = ims.Graph(g.n, g.offsets, g.indices, model, param)
@@ -463,13 +469,16 @@ def test_batch_equals_single_runs_across_graph_replays(ims):
         it[0].close()
 
 
-@pytest.mark.parametrize("split", [2, 16, 64])
+@pytest.mark.parametrize("split", [2, 8, 16, 64])
 def test_batch_split_tasks_equal_single_runs(ims, split):
     """Words split into `split` tasks of 64 / split trials each (trial
     counts with ragged last words: parts past the last trial are skipped)
-    give the per-item results of whole-word runs, over two replays."""
+    give the per-item results of whole-word runs, over two replays.  From 8
+    on a task's trials lie in one 8-trial group and lanes take whole nodes
+    (hubs with more arcs go through the wavefront-wide walk); LT items with
+    equal and with unequal in-weights."""
     import torch
-    items, specs = _batch_items(ims)
+    items, specs = _batch_items(ims, count=12, unequal_lt=True)
     singles = [ims.simulate(G, sd, T, rs) for (G, sd, T, rs) in items]
     B = ims.Batch(items, tuning=(2, 0, split))
     for rep in range(2):
