@@ -115,6 +115,7 @@ struct ims_graph {
     Buf A, N[3], Q[3], aux, thp, Anm, nmark;
     // sets mode (ims_simulate_sets): per-slot state
     Buf sA, sN, sQ[3], sact, sstamp, ssteps, sets_dev;
+    imsim::BatchItem* d_item = nullptr;  // the single-run slot form's item
     bool sets_zero_dirty = true;  // sN / sstamp / ssteps must start zeroed
     bool zero_dirty = true;  // N / aux must be zero between runs
     uint32_t* d_qcount = nullptr;
@@ -149,6 +150,7 @@ struct ims_graph {
         release(thp);
         release(Anm);
         for (Buf* b : {&sA, &sN, &sQ[0], &sQ[1], &sQ[2], &sact, &sstamp, &ssteps, &sets_dev}) release(*b);
+        dev_free(d_item);
         dev_free(d_off);
         dev_free(d_idx);
         dev_free(d_thr);
@@ -506,8 +508,34 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
         return IMS_OK;
     }
 
-    if (!active_bits && (rc = ensure_buf(g, g->A, cells * 8, false))) return rc;
-    if (shape == 1) {
+    // word-local runs that return only counts take the slot form: each word
+    // runs as four 16-trial tasks on workgroup slots whose state is cleared
+    // sparsely, and the tasks add their own counts (no fill of the full
+    // state, no reduction passes over it)
+    const bool slot_run = shape == 1 && !active_bits && !level_counts;
+    const uint32_t slot_sp = 2;
+    const uint64_t slot_tasks = (uint64_t)W << slot_sp;
+    const int slot_per_cu = opts && opts->blocks_per_cu > 0 ? opts->blocks_per_cu : 2;
+    const uint64_t slots = std::max<uint64_t>(1, std::min<uint64_t>(slot_tasks, (uint64_t)g->cus * slot_per_cu));
+    if (slot_run) {
+        const uint64_t sc = slots * n;
+        const uint64_t before = g->sA.bytes + g->sN.bytes + g->sstamp.bytes + g->ssteps.bytes;
+        if ((rc = ensure_buf(g, g->sA, sc * 8, false)) || (rc = ensure_buf(g, g->sact, sc * 4, false)) ||
+            (rc = ensure_buf(g, g->sQ[0], sc * 4, false)) || (rc = ensure_buf(g, g->sQ[1], sc * 4, false)) ||
+            (rc = ensure_buf(g, g->sN, sc * 8, false)) || (rc = ensure_buf(g, g->sQ[2], sc * 16, false)) ||
+            (rc = ensure_buf(g, g->sstamp, sc * 4, false)) || (rc = ensure_buf(g, g->ssteps, slots * 4, false)))
+            return rc;
+        if (g->sA.bytes + g->sN.bytes + g->sstamp.bytes + g->ssteps.bytes != before) {
+            // fresh slot state starts clear (tasks leave it clear)
+            for (ims_graph::Buf* b : {&g->sA, &g->sN, &g->sstamp, &g->ssteps})
+                if ((rc = fill_async<uint8_t>((uint8_t*)b->p, b->bytes, 0, s))) return rc;
+            g->sets_zero_dirty = false;
+        }
+        if (!g->d_item && (rc = dev_alloc(&g->d_item, 1))) return rc;
+    }
+    if (!active_bits && !slot_run && (rc = ensure_buf(g, g->A, cells * 8, false))) return rc;
+    if (slot_run) {
+    } else if (shape == 1) {
         if (g->model == IMS_MODEL_IC) {
             if ((rc = ensure_buf(g, g->N[0], cells * 8, true))) return rc;
             if ((rc = ensure_buf(g, g->Q[0], cells * 4, false))) return rc;
@@ -565,7 +593,7 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
     // the LT grid shape keeps its state node-major and writes A (when asked
     // for) from it at the end
     const bool ltg = shape == 2 && g->model == IMS_MODEL_LT;
-    if (!ltg && (rc = fill_async<uint64_t>(A, cells, 0ull, s))) return rc;
+    if (!ltg && !slot_run && (rc = fill_async<uint64_t>(A, cells, 0ull, s))) return rc;
     if (g->zero_dirty) {
         for (auto& b : g->N)
             if (b.p && (rc = fill_async<uint8_t>((uint8_t*)b.p, b.bytes, 0, s))) return rc;
@@ -635,7 +663,29 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
             if (!g->prof_ev[2 * slot + k]) IMS_HIP(hipEventCreate(&g->prof_ev[2 * slot + k]));
         IMS_HIP(hipEventRecord(g->prof_ev[2 * slot], s));
     }
-    if (shape == 1) {
+    if (slot_run) {
+        if (node_counts && (rc = fill_async<uint32_t>(node_counts, n, 0u, s))) return rc;
+        imsim::BatchItem it;
+        std::memset(&it, 0, sizeof it);
+        it.P = P;
+        it.model = g->model;
+        it.trial_counts = trial_counts;
+        it.node_counts = node_counts;
+        it.total = total;
+        IMS_HIP(hipMemcpyAsync(g->d_item, &it, sizeof it, hipMemcpyHostToDevice, s));
+        imsim::SlotBufs S{n,
+                          (uint64_t*)g->sA.p,
+                          (uint64_t*)g->sN.p,
+                          (uint32_t*)g->sQ[0].p,
+                          (uint32_t*)g->sQ[1].p,
+                          (uint64_t*)g->sQ[2].p,
+                          (uint32_t*)g->sact.p,
+                          (uint32_t*)g->sstamp.p,
+                          (uint32_t*)g->ssteps.p};
+        hipLaunchKernelGGL(imsim::slot_run_kernel, dim3((uint32_t)slots), dim3(imsim::kTaskBlock), 0, s, (const imsim::BatchItem*)g->d_item,
+                           slot_sp, (uint32_t)slot_tasks, g->d_status + 2, S, g->d_status);
+        IMS_HIP(hipGetLastError());
+    } else if (shape == 1) {
         const int per_cu = opts && opts->blocks_per_cu > 0 ? opts->blocks_per_cu : 2;
         const uint32_t blocks = std::min<uint32_t>(W, (uint32_t)(g->cus * per_cu));
         if (g->model == IMS_MODEL_IC)
@@ -752,7 +802,7 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
     }
     g->last_shape = (uint32_t)shape;
 
-    if (n > 0 && !(ltg && cells > 0)) {
+    if (n > 0 && !(ltg && cells > 0) && !slot_run) {
         const uint64_t nblk = std::min<uint64_t>((n + imsim::kBlock - 1) / imsim::kBlock, 1024);
         hipLaunchKernelGGL(imsim::reduce_trial_counts, dim3((unsigned)nblk, W), dim3(imsim::kBlock), 0, s, A, g->n, n_trials,
                            trial_counts);
@@ -1028,10 +1078,17 @@ int batch_enqueue(ims_batch* b, hipStream_t s)
         if ((rc = fill_async<unsigned long long>((unsigned long long*)it.total, 1, 0ull, s))) return rc;
     }
     if ((rc = fill_async<uint32_t>(b->d_ctl, 4, 0u, s))) return rc;
+    imsim::SlotBufs S{b->max_n,
+                      (uint64_t*)b->sA.p,
+                      (uint64_t*)b->sN.p,
+                      (uint32_t*)b->sQ0.p,
+                      (uint32_t*)b->sQ1.p,
+                      (uint64_t*)b->sQ2.p,
+                      (uint32_t*)b->sact.p,
+                      (uint32_t*)b->sstamp.p,
+                      (uint32_t*)b->ssteps.p};
     hipLaunchKernelGGL(imsim::batch_kernel, dim3(b->slots), dim3(imsim::kTaskBlock), 0, s, (const imsim::BatchItem*)b->d_items,
-                       (const uint64_t*)b->d_tasks, b->n_tasks, b->d_ctl, b->max_n, (uint64_t*)b->sA.p, (uint64_t*)b->sN.p,
-                       (uint32_t*)b->sQ0.p, (uint32_t*)b->sQ1.p, (uint64_t*)b->sQ2.p, (uint32_t*)b->sact.p, (uint32_t*)b->sstamp.p,
-                       (uint32_t*)b->ssteps.p, b->d_ctl + 1);
+                       (const uint64_t*)b->d_tasks, b->n_tasks, b->d_ctl, S, b->d_ctl + 1);
     IMS_HIP(hipGetLastError());
     return IMS_OK;
 }

@@ -1916,13 +1916,30 @@ __device__ __forceinline__ uint64_t split_mask(uint32_t s, uint32_t part)
     return s == 0 ? ~0ull : ((1ull << width) - 1ull) << (width * part);
 }
 
-__global__ __launch_bounds__(kTaskBlock, 4) void batch_kernel(const BatchItem* __restrict__ items, const uint64_t* __restrict__ tasks,
-                                                       uint32_t n_tasks, uint32_t* task_counter, uint64_t max_n,
-                                                       uint64_t* sA, uint64_t* sN, uint32_t* sQ0, uint32_t* sQ1, uint64_t* sQ2,
-                                                       uint32_t* sact, uint32_t* sstamp, uint32_t* slot_steps, uint32_t* status)
+// Slot state of the batch and single-run slot forms: rows of max_n entries
+// per workgroup slot.
+struct SlotBufs {
+    uint64_t max_n;
+    uint64_t* sA;
+    uint64_t* sN;
+    uint32_t* sQ0;
+    uint32_t* sQ1;
+    uint64_t* sQ2;
+    uint32_t* sact;
+    uint32_t* sstamp;
+    uint32_t* slot_steps;
+};
+
+// The persistent loop of the slot forms: workgroups take task indices from
+// the counter; task_of(t, item, w, s, part) names the task's item, word and
+// trial part.
+template <typename TaskOf>
+__device__ __forceinline__ void slot_tasks(TaskOf task_of, uint32_t n_tasks, uint32_t* task_counter, const SlotBufs& S,
+                                           uint32_t* status)
 {
     __shared__ TaskShared sh;
     const uint64_t slot = blockIdx.x;
+    const uint64_t max_n = S.max_n;
     uint32_t max_steps = 0;
     bool guard = false;
     for (;;) {
@@ -1931,34 +1948,33 @@ __global__ __launch_bounds__(kTaskBlock, 4) void batch_kernel(const BatchItem* _
         __syncthreads();
         const uint32_t t = sh.task;
         if (t >= n_tasks) break;
-        const uint64_t code = tasks[t];
-        const BatchItem& it = items[code >> 32];
+        const BatchItem* itp;
+        uint32_t w, sp, part;
+        task_of(t, itp, w, sp, part);
+        const BatchItem& it = *itp;
         const SimParams& P = it.P;
         TaskCtx c;
-        c.w = (uint32_t)code & 0xFFFFu;
-        {
-            const uint32_t sp = ((uint32_t)code >> 24) & 7u, part = ((uint32_t)code >> 16) & 63u;
-            c.tmask = split_mask(sp, part);
-            c.group = sp >= 3 ? (part << (6 - sp)) >> 3 : 8u;
-        }
+        c.w = w;
+        c.tmask = split_mask(sp, part);
+        c.group = sp >= 3 ? (part << (6 - sp)) >> 3 : 8u;
         c.seeds = P.seeds;
         c.n_seeds = P.n_seeds;
-        c.act = sact + slot * max_n;
-        c.Aw = sA + slot * max_n;
+        c.act = S.sact + slot * max_n;
+        c.Aw = S.sA + slot * max_n;
         c.Bw = nullptr;
-        c.L[0] = sQ0 + slot * max_n;
-        c.L[1] = sQ1 + slot * max_n;
-        c.Nw = sN + slot * max_n;
-        c.M[0] = sQ2 + slot * max_n * 2;
+        c.L[0] = S.sQ0 + slot * max_n;
+        c.L[1] = S.sQ1 + slot * max_n;
+        c.Nw = S.sN + slot * max_n;
+        c.M[0] = S.sQ2 + slot * max_n * 2;
         c.M[1] = c.M[0] + max_n;
-        c.C = (uint32_t*)(sQ2 + slot * max_n * 2);
-        c.stamp = sstamp + slot * max_n;
-        if (threadIdx.x == 0) sh.base = slot_steps[slot];
+        c.C = (uint32_t*)(S.sQ2 + slot * max_n * 2);
+        c.stamp = S.sstamp + slot * max_n;
+        if (threadIdx.x == 0) sh.base = S.slot_steps[slot];
         __syncthreads();
         c.stamp_base = sh.base;
         const bool lt = it.model != 0;
         const uint32_t steps = lt ? lt_task(P, c, sh, guard) : ic_task(P, c, sh, guard);
-        if (threadIdx.x == 0 && lt) slot_steps[slot] = c.stamp_base + steps + 1;
+        if (threadIdx.x == 0 && lt) S.slot_steps[slot] = c.stamp_base + steps + 1;
         finish_slot_task(c, sh.act, sh, it.total, it.node_counts, it.trial_counts, P.T);
         max_steps = steps > max_steps ? steps : max_steps;
     }
@@ -1966,6 +1982,36 @@ __global__ __launch_bounds__(kTaskBlock, 4) void batch_kernel(const BatchItem* _
         atomicMax(&status[0], max_steps);
         if (guard) status[1] = 1;
     }
+}
+
+__global__ __launch_bounds__(kTaskBlock, 4) void batch_kernel(const BatchItem* __restrict__ items, const uint64_t* __restrict__ tasks,
+                                                       uint32_t n_tasks, uint32_t* task_counter, SlotBufs S, uint32_t* status)
+{
+    slot_tasks(
+        [&](uint32_t t, const BatchItem*& itp, uint32_t& w, uint32_t& sp, uint32_t& part) {
+            const uint64_t code = tasks[t];
+            itp = &items[code >> 32];
+            w = (uint32_t)code & 0xFFFFu;
+            sp = ((uint32_t)code >> 24) & 7u;
+            part = ((uint32_t)code >> 16) & 63u;
+        },
+        n_tasks, task_counter, S, status);
+}
+
+// Single-run slot form: one item whose words run as 2^sp tasks each (task t =
+// word t >> sp, part t & (2^sp - 1)); counts and the total accumulate into
+// the item's outputs as in the batch form.
+__global__ __launch_bounds__(kTaskBlock, 4) void slot_run_kernel(const BatchItem* __restrict__ item, uint32_t sp, uint32_t n_tasks,
+                                                          uint32_t* task_counter, SlotBufs S, uint32_t* status)
+{
+    slot_tasks(
+        [&](uint32_t t, const BatchItem*& itp, uint32_t& w, uint32_t& spo, uint32_t& part) {
+            itp = item;
+            w = t >> sp;
+            spo = sp;
+            part = t & ((1u << sp) - 1u);
+        },
+        n_tasks, task_counter, S, status);
 }
 
 // ============================================================ reductions

@@ -35,6 +35,12 @@ def run_both(ims, model, n, off, idx, param, seeds, T, rs, t_sample=None, opts=N
     bits = got["active_bits"].cpu().numpy().view(np.uint64)
     tc = got["trial_counts"].cpu().numpy().view(np.uint32)
     nc = got["node_counts"].cpu().numpy().view(np.uint32)
+    # the same run returning counts only (the word-local shape then runs
+    # 16-trial slot tasks that add their own counts)
+    cnt_only = ims.simulate(G, seeds, T, rs, want_bits=False, opts=opts)
+    assert cnt_only["total"] == got["total"]
+    assert (cnt_only["trial_counts"].cpu().numpy().view(np.uint32) == tc).all()
+    assert (cnt_only["node_counts"].cpu().numpy().view(np.uint32) == nc).all()
     enc = oracle.encode(model, param) if np.asarray(param).dtype == np.float64 else param
     if t_sample is None:
         ref = oracle.simulate(model, n, off, idx, enc, seeds, T, rs, threads=8)
