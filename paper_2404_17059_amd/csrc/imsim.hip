@@ -776,6 +776,13 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
             done = g->h_flag[0] == 0 || end >= g->cap;
             next = end;
         }
+        // IC: level `next` is empty and was not launched; launching it clears
+        // the frontier masks of level next - 1 (the last expanded level), which
+        // must be zero when the next run starts
+        if (g->model == IMS_MODEL_IC && next < g->cap) {
+            hipLaunchKernelGGL(imsim::grid_ic_level_kernel, dim3(blocks), dim3(imsim::kBlock), 0, s, P, next);
+            IMS_HIP(hipGetLastError());
+        }
         // number of steps: first step counter that is zero
         std::vector<uint32_t> qc(std::min<uint32_t>(next + 1, g->cap));
         IMS_HIP(hipMemcpy(qc.data(), g->d_qcount, qc.size() * sizeof(uint32_t), hipMemcpyDeviceToHost));
@@ -784,6 +791,7 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
         if (g->model == IMS_MODEL_LT) steps += 1;
         g->last_steps = steps;
         if (next >= g->cap && qc.back() != 0) {
+            g->zero_dirty = true;  // a cut-off run leaves frontier masks behind
             uint32_t one = 1;
             IMS_HIP(hipMemcpyAsync(g->d_status + 1, &one, sizeof one, hipMemcpyHostToDevice, s));
         }

@@ -114,6 +114,24 @@ def test_ic_probability_extremes(ims):
     assert (got["node_counts"].cpu().numpy() == 100 * reach).all()
 
 
+def test_ic_grid_repeated_runs_start_clean(ims):
+    """Runs on one graph handle leave no frontier masks behind, whichever
+    level the last step launch ends on: a path 0 -> 1 -> ... -> K-1 with p = 1
+    is run from node 0 (K levels), then from node K-3, which must reach the
+    last three nodes in every trial."""
+    opts = ims.Opts(shape=2, blocks_per_cu=0, alpha=0.0, profile=0)
+    for K in range(3, 40):
+        src = np.arange(K - 1)
+        off, idx = pins.csr_from_arcs(K, src, src + 1)
+        G = ims.Graph(K, off, idx, "ic", np.ones(K - 1))
+        for rep in range(2):
+            r = ims.simulate(G, [0], 64, 11, opts=opts)
+            assert r["total"] == K * 64, (K, rep)
+        r = ims.simulate(G, [K - 3], 64, 12, opts=opts)
+        assert r["total"] == 3 * 64, K
+        G.close()
+
+
 def test_lt_full_weight_arcs(ims):
     # indegree-1 nodes carry a weight of exactly 2^32 (stored as two pieces)
     n = 200
