@@ -594,6 +594,10 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
     // for) from it at the end
     const bool ltg = shape == 2 && g->model == IMS_MODEL_LT;
     if (!ltg && !slot_run && (rc = fill_async<uint64_t>(A, cells, 0ull, s))) return rc;
+    // LT word-local steps stamp candidates 1, 2, ... in aux, which earlier
+    // runs (of either shape) leave holding their own stamps and sweep marks
+    if (shape == 1 && !slot_run && g->model == IMS_MODEL_LT && (rc = fill_async<uint32_t>((uint32_t*)g->aux.p, cells, 0u, s)))
+        return rc;
     if (g->zero_dirty) {
         for (auto& b : g->N)
             if (b.p && (rc = fill_async<uint8_t>((uint8_t*)b.p, b.bytes, 0, s))) return rc;

@@ -132,6 +132,28 @@ def test_ic_grid_repeated_runs_start_clean(ims):
         G.close()
 
 
+@pytest.mark.parametrize("first_shape", [1, 2])
+def test_lt_word_local_runs_after_other_runs(ims, first_shape):
+    """LT word-local runs (active bits, per-level counts) on a handle that
+    already ran give what they give on a fresh handle."""
+    g = synth.erdos_renyi_directed(3000, 6.0, seed=21)
+    param = synth.weighted_cascade(g)
+    seeds = synth.random_seeds(g.n, 10, 22)
+    fresh = ims.Graph(g.n, g.offsets, g.indices, "lt", param)
+    ref_bits = ims.simulate(fresh, seeds, 200, 5, want_bits=True, opts=ims.Opts(shape=1, blocks_per_cu=0, alpha=0.0, profile=0))
+    ref_lv = ims.simulate_levels(fresh, seeds, 200, 5)
+    fresh.close()
+    G = ims.Graph(g.n, g.offsets, g.indices, "lt", param)
+    ims.simulate(G, seeds, 200, 4, want_bits=True, opts=ims.Opts(shape=first_shape, blocks_per_cu=0, alpha=0.0, profile=0))
+    for rep in range(2):
+        got = ims.simulate(G, seeds, 200, 5, want_bits=True, opts=ims.Opts(shape=1, blocks_per_cu=0, alpha=0.0, profile=0))
+        assert (got["active_bits"].cpu().numpy() == ref_bits["active_bits"].cpu().numpy()).all(), rep
+        lv = ims.simulate_levels(G, seeds, 200, 5)
+        assert lv["levels_processed"] == ref_lv["levels_processed"]
+        assert (lv["level_counts"] == ref_lv["level_counts"]).all(), rep
+    G.close()
+
+
 def test_lt_full_weight_arcs(ims):
     # indegree-1 nodes carry a weight of exactly 2^32 (stored as two pieces)
     n = 200
