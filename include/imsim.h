@@ -95,8 +95,9 @@ int ims_graph_info(const ims_graph* g, int64_t* n, int64_t* m, int* model);
 typedef struct ims_opts {
     int shape;             /* 0 = auto (IC: word-local when the run has at least a quarter as
                               many 64-trial words as compute units, else grid-wide; LT: grid-
-                              wide), 1 = word-local
-                              (one workgroup per 64-trial word runs its whole cascade), 2 = grid-
+                              wide), 1 = word-local (a workgroup runs the whole cascade of its
+                              trials: of one 64-trial word when active_bits is requested, else of
+                              16 trials on persistent slots that add their own counts), 2 = grid-
                               wide steps (one launch per level / sweep) */
     int32_t blocks_per_cu; /* workgroups per compute unit; 0 = auto */
     double alpha;          /* LT grid shape: a sweep marks out-neighbours of joining nodes (and the
