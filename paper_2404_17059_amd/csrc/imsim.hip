@@ -174,6 +174,8 @@ namespace {
 
 // Device bytes the LT threshold table may take (W * n * 256).
 constexpr uint64_t kThresholdTableBudget = 32ull << 30;
+// device memory the single-run slot form may hold (48 B per slot and node)
+constexpr uint64_t kSlotStateBudget = 32ull << 30;
 
 // Grow a workspace buffer to at least `bytes`; a fresh buffer may hold garbage.
 int ensure_buf(ims_graph* g, ims_graph::Buf& b, uint64_t bytes, bool zero_invariant)
@@ -512,11 +514,13 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
     // runs as four 16-trial tasks on workgroup slots whose state is cleared
     // sparsely, and the tasks add their own counts (no fill of the full
     // state, no reduction passes over it)
-    const bool slot_run = shape == 1 && !active_bits && !level_counts;
+    // (graphs whose slot state would exceed kSlotStateBudget keep one
+    // workgroup per word over the W x n state)
     const uint32_t slot_sp = 2;
     const uint64_t slot_tasks = (uint64_t)W << slot_sp;
     const int slot_per_cu = opts && opts->blocks_per_cu > 0 ? opts->blocks_per_cu : 2;
     const uint64_t slots = std::max<uint64_t>(1, std::min<uint64_t>(slot_tasks, (uint64_t)g->cus * slot_per_cu));
+    const bool slot_run = shape == 1 && !active_bits && !level_counts && slots * n * 48 <= kSlotStateBudget;
     if (slot_run) {
         const uint64_t sc = slots * n;
         const uint64_t before = g->sA.bytes + g->sN.bytes + g->sstamp.bytes + g->ssteps.bytes;
