@@ -515,7 +515,7 @@ def test_batch_equals_single_runs_across_graph_replays(ims):
         it[0].close()
 
 
-@pytest.mark.parametrize("split", [2, 8, 16, 64])
+@pytest.mark.parametrize("split", [1, 2, 4, 8, 16, 32, 64])
 def test_batch_split_tasks_equal_single_runs(ims, split):
     """Words split into `split` tasks of 64 / split trials each (trial
     counts with ragged last words: parts past the last trial are skipped)
@@ -535,6 +535,33 @@ def test_batch_split_tasks_equal_single_runs(ims, split):
             assert r["total"] == s1["total"], (rep, k)
             assert (r["trial_counts"] == s1["trial_counts"].cpu().numpy().view(np.uint32)).all(), (rep, k)
             assert (r["node_counts"] == s1["node_counts"].cpu().numpy().view(np.uint32)).all(), (rep, k)
+    B.close()
+    for it in items:
+        it[0].close()
+
+
+def test_batch_64_items_full(ims):
+    """The 64-item uneven batch (ER / BA, IC-WC / LT-1/indeg, n 1k-200k, 2,000
+    trials each) in one persistent launch with the default schedule: every
+    item's per-trial counts, per-node counts and total equal the oracle's over
+    all trials."""
+    import os
+
+    import torch
+    ws = synth.batch_items()
+    items = [(ims.Graph(w.graph.n, w.graph.offsets, w.graph.indices, w.model, w.param), w.seeds, w.n_trials, w.rng_seed)
+             for w in ws]
+    B = ims.Batch(items)
+    say("[parity] batch of 64 items, default schedule")
+    B.launch()
+    torch.cuda.synchronize()
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    for k, (w, r) in enumerate(zip(ws, B.results())):
+        ref = oracle.simulate(w.model, w.graph.n, w.graph.offsets, w.graph.indices, oracle.encode(w.model, w.param),
+                              w.seeds, w.n_trials, w.rng_seed, threads=threads, want_bits=False)
+        assert r["total"] == ref["total"], (k, w.name)
+        assert (r["trial_counts"] == ref["trial_counts"]).all(), (k, w.name)
+        assert (r["node_counts"] == ref["node_counts"]).all(), (k, w.name)
     B.close()
     for it in items:
         it[0].close()
