@@ -538,8 +538,7 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
         if (!g->d_item && (rc = dev_alloc(&g->d_item, 1))) return rc;
     }
     if (!active_bits && !slot_run && (rc = ensure_buf(g, g->A, cells * 8, false))) return rc;
-    if (slot_run) {
-    } else if (shape == 1) {
+    if (shape == 1 && !slot_run) {
         if (g->model == IMS_MODEL_IC) {
             if ((rc = ensure_buf(g, g->N[0], cells * 8, true))) return rc;
             if ((rc = ensure_buf(g, g->Q[0], cells * 4, false))) return rc;
@@ -552,13 +551,13 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
             // synchronous steps (level counts) hold each step's joins here
             if (level_counts && (rc = ensure_buf(g, g->N[0], cells * 8, true))) return rc;
         }
-    } else if (g->model == IMS_MODEL_IC) {
+    } else if (shape == 2 && g->model == IMS_MODEL_IC) {
         const uint64_t qcap = (uint64_t)W * std::max<uint64_t>(g->total_chunks, 1);
         for (int i = 0; i < 3; ++i) {
             if ((rc = ensure_buf(g, g->N[i], cells * 8, true))) return rc;
             if ((rc = ensure_buf(g, g->Q[i], qcap * 8, false))) return rc;
         }
-    } else {
+    } else if (shape == 2) {
         if ((rc = ensure_buf(g, g->aux, cells * 4, true))) return rc;
         if ((rc = ensure_buf(g, g->Anm, cells * 8, false))) return rc;
         if ((rc = ensure_buf(g, g->nmark, (uint64_t)g->n * 4, false))) return rc;
