@@ -1354,9 +1354,14 @@ constexpr int kTaskBlock = 512;  // word-local workgroup: 8 wavefronts per task
 constexpr int kTaskWaves = kTaskBlock / 64;
 
 // Workgroup-shared scratch of one task.
+constexpr uint32_t kBigDeg = 512;  // out-arcs above which the whole workgroup walks a frontier node
+constexpr uint32_t kBigMax = 64;   // such nodes handed over per step (more are walked by one wavefront)
+
 struct TaskShared {
     uint32_t cnt[2];
     uint32_t next_item;
+    uint32_t nbig;
+    uint32_t big[kBigMax];  // frontier-list positions of the nodes the workgroup walks together
     uint32_t cand;
     uint32_t act;
     uint32_t base;
@@ -1411,6 +1416,19 @@ __device__ __forceinline__ void flush_level(const SimParams& P, TaskShared& sh, 
 // more arcs go through the wavefront-wide walk.
 constexpr uint32_t kNarrowDeg = 16;
 
+// Called by a whole wavefront: hand frontier-list position `it` (a node with
+// more than kBigDeg out-arcs) to the whole workgroup, which walks it after
+// this pass; false when kBigMax nodes were already handed over this step.
+__device__ __forceinline__ bool hand_over(uint32_t it, uint32_t lane, TaskShared& sh)
+{
+    uint32_t pos = 0;
+    if (lane == 0) pos = atomicAdd(&sh.nbig, 1u);
+    pos = uniform32(__shfl(pos, 0));
+    if (pos >= kBigMax) return false;
+    if (lane == 0) sh.big[pos] = it;
+    return true;
+}
+
 // IC cascade of one task.  Per step every wavefront takes frontier entries
 // and walks their out-arcs lane-strided; a node's first new bit of the step
 // appends it to the next list (counter in LDS); after a barrier the next
@@ -1461,6 +1479,7 @@ __device__ __forceinline__ uint32_t ic_task(const SimParams& P, const TaskCtx& c
         if (threadIdx.x == 0) {
             sh.cnt[nxt] = 0;
             sh.next_item = 0;
+            sh.nbig = 0;
         }
         __syncthreads();
         // one out-arc e = (u, v) of a frontier node whose new trials are `mask`
@@ -1508,6 +1527,7 @@ __device__ __forceinline__ uint32_t ic_task(const SimParams& P, const TaskCtx& c
                 while (big) {
                     const int j = __builtin_ctzll(big);
                     big &= big - 1;
+                    if (uniform32(__shfl(deg, j)) > kBigDeg && hand_over(it + (uint32_t)j, lane, sh)) continue;
                     const uint32_t ub = uniform32(__shfl(u, j));
                     const uint64_t mb = uniform64(__shfl(mask, j));
                     const int64_t e1 = P.off[ub + 1];
@@ -1522,8 +1542,21 @@ __device__ __forceinline__ uint32_t ic_task(const SimParams& P, const TaskCtx& c
                 if (it >= cnt) break;
                 const uint32_t u = (cur ? c.L[1] : c.L[0])[it];
                 const uint64_t mask = (cur ? c.M[1] : c.M[0])[it];
+                const int64_t e0 = P.off[u], e1 = P.off[u + 1];
+                if ((uint64_t)(e1 - e0) > kBigDeg && hand_over(it, lane, sh)) continue;
+                for (int64_t e = e0 + lane; e < e1; e += 64) exam(e, P.idx[e], P.thr[e], mask);
+            }
+        }
+        // the handed-over nodes, every wavefront on each
+        __syncthreads();
+        {
+            const uint32_t nb = sh.nbig < kBigMax ? sh.nbig : kBigMax;
+            for (uint32_t b = 0; b < nb; ++b) {
+                const uint32_t it = sh.big[b];
+                const uint32_t u = (cur ? c.L[1] : c.L[0])[it];
+                const uint64_t mask = (cur ? c.M[1] : c.M[0])[it];
                 const int64_t e1 = P.off[u + 1];
-                for (int64_t e = P.off[u] + lane; e < e1; e += 64) exam(e, P.idx[e], P.thr[e], mask);
+                for (int64_t e = P.off[u] + threadIdx.x; e < e1; e += kTaskBlock) exam(e, P.idx[e], P.thr[e], mask);
             }
         }
         __syncthreads();
@@ -1652,6 +1685,7 @@ __device__ __forceinline__ uint32_t lt_task(const SimParams& P, const TaskCtx& c
             sh.cnt[nxt] = 0;
             sh.cand = 0;
             sh.next_item = 0;
+            sh.nbig = 0;
         }
         __syncthreads();
         // push side: out-neighbours of the frontier with an inactive trial
@@ -1682,6 +1716,7 @@ __device__ __forceinline__ uint32_t lt_task(const SimParams& P, const TaskCtx& c
                 while (big) {
                     const int j = __builtin_ctzll(big);
                     big &= big - 1;
+                    if (uniform32(__shfl(deg, j)) > kBigDeg && hand_over(it + (uint32_t)j, lane, sh)) continue;
                     const uint32_t ub = uniform32(__shfl(u, j));
                     const int64_t e1 = P.off[ub + 1];
                     for (int64_t e = P.off[ub] + lane; e < e1; e += 64) collect(P.idx[e]);
@@ -1694,8 +1729,19 @@ __device__ __forceinline__ uint32_t lt_task(const SimParams& P, const TaskCtx& c
                 it = __shfl(it, 0);
                 if (it >= cnt) break;
                 const uint32_t u = (cur ? c.L[1] : c.L[0])[it];
+                const int64_t e0 = P.off[u], e1 = P.off[u + 1];
+                if ((uint64_t)(e1 - e0) > kBigDeg && hand_over(it, lane, sh)) continue;
+                for (int64_t e = e0 + lane; e < e1; e += 64) collect(P.idx[e]);
+            }
+        }
+        // the handed-over nodes, every wavefront on each
+        __syncthreads();
+        {
+            const uint32_t nb = sh.nbig < kBigMax ? sh.nbig : kBigMax;
+            for (uint32_t b = 0; b < nb; ++b) {
+                const uint32_t u = (cur ? c.L[1] : c.L[0])[sh.big[b]];
                 const int64_t e1 = P.off[u + 1];
-                for (int64_t e = P.off[u] + lane; e < e1; e += 64) collect(P.idx[e]);
+                for (int64_t e = P.off[u] + threadIdx.x; e < e1; e += kTaskBlock) collect(P.idx[e]);
             }
         }
         __syncthreads();
