@@ -180,9 +180,10 @@ int ims_simulate_sets_from(ims_graph* g, const uint64_t* base_bits, const uint32
                            const ims_opts* opts, uint64_t* totals, uint32_t* node_counts, void* stream);
 
 /* Batch: several (graph, seeds, trials, rng_seed) runs, IC and LT mixed,
- * executed by one persistent launch that takes (item, 64-trial word) tasks
- * in a scheduled order, captured once in a HIP graph and replayed.  Each
- * item's outputs equal those of ims_simulate on that item alone. */
+ * executed by one persistent launch that takes (item, 64-trial word, trial
+ * part) tasks in a scheduled order, captured once in a HIP graph and
+ * replayed.  Each item's outputs equal those of ims_simulate on that item
+ * alone. */
 typedef struct ims_batch ims_batch;
 
 typedef struct ims_batch_item {
@@ -199,17 +200,19 @@ typedef struct ims_batch_item {
 typedef struct ims_tuning {
     int32_t blocks_per_cu;  /* persistent workgroups per compute unit (1..16) */
     int32_t order;          /* 0 = items by estimated cost, largest first; 1 = item order */
-    int32_t split;          /* tasks per 64-trial word: 1, 2, 4, ... 64 trials per task = 64 / split
-                               (rounded down to a power of two; values below 1 mean 1).  A task runs
-                               the cascade of its trials alone, so a split shortens the longest
-                               task at the cost of more, smaller tasks; results do not change */
+    int32_t split;          /* tasks per 64-trial word, 1 .. 64 (rounded down to a power of two;
+                               values below 1 mean 1); each task takes 64 / split of the word's
+                               trials and runs their cascade alone, so a split shortens the
+                               longest task at the cost of more, smaller tasks; results do not
+                               change */
 } ims_tuning;
 
 /* tuning NULL = defaults (2 per CU, largest first, 8 tasks per word).  Synchronous. */
 int ims_batch_create(const ims_batch_item* items, uint32_t n_items, const ims_tuning* tuning, ims_batch** out);
-/* Time every candidate schedule `repeats` times on `stream`, check that all
- * give identical outputs, keep the fastest (reported in *chosen if not NULL)
- * and drop the captured graph.  Synchronous. */
+/* Time every candidate schedule (workgroups per compute unit, order, split)
+ * `repeats` times on `stream`, check that all give identical outputs, keep
+ * the fastest (reported in *chosen if not NULL) and drop the captured graph.
+ * Synchronous. */
 int ims_batch_autotune(ims_batch* b, int repeats, void* stream, ims_tuning* chosen);
 /* Run the batch on `stream`: the first call (and the first after a tuning
  * change) captures the launch sequence into a HIP graph, later calls replay
