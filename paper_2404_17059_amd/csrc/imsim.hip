@@ -805,7 +805,7 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
         IMS_HIP(hipMemcpyAsync(g->d_status, &steps, sizeof steps, hipMemcpyHostToDevice, s));
         IMS_HIP(hipStreamSynchronize(s));
         if (g->model == IMS_MODEL_LT && cells > 0) {
-            hipLaunchKernelGGL(imsim::ltg_finish_kernel, dim3((uint32_t)std::min<uint64_t>(g->cus, ((uint64_t)g->n + 255) / 256)),
+            hipLaunchKernelGGL(imsim::ltg_finish_kernel, dim3((uint32_t)std::min<uint64_t>((uint64_t)g->cus * 4, ((uint64_t)g->n + 255) / 256)),
                                dim3(imsim::kBlock), 0, s, (const uint64_t*)P.Anm, active_bits, g->n, W, n_trials, trial_counts,
                                node_counts, (unsigned long long*)total, accumulate ? 1 : 0);
             IMS_HIP(hipGetLastError());
