@@ -1181,12 +1181,13 @@ __global__ __launch_bounds__(kBlock, 4) void ltg_sweep_kernel(SimParams P, uint3
 #pragma unroll
                         for (uint32_t y = 0; y < kRowWords; ++y) R[lane * kRowPitch + y] = lane < total ? row[y] : 0ull;
                     } else {
-                        // odd word count or a short last group: word by word
-#pragma unroll 1
-                        for (uint32_t y = 0; y < kRowWords; ++y) {
-                            const uint64_t m = rp[y < gw ? y : 0u];
-                            R[lane * kRowPitch + y] = lane < total && y < gw ? m : 0ull;
-                        }
+                        // odd word count or a short last group: 8-byte loads,
+                        // all issued before the first is stored
+                        uint64_t row[kRowWords];
+#pragma unroll
+                        for (uint32_t y = 0; y < kRowWords; ++y) row[y] = rp[y < gw ? y : 0u];
+#pragma unroll
+                        for (uint32_t y = 0; y < kRowWords; ++y) R[lane * kRowPitch + y] = lane < total && y < gw ? row[y] : 0ull;
                     }
                     __builtin_amdgcn_wave_barrier();
                 }
