@@ -116,7 +116,7 @@ struct ims_graph {
     // sets mode (ims_simulate_sets): per-slot state
     Buf sA, sN, sQ[3], sact, sstamp, ssteps, sets_dev;
     imsim::BatchItem* d_item = nullptr;  // the single-run slot form's item
-    bool sets_zero_dirty = true;  // sN / sstamp / ssteps must start zeroed
+    bool sets_zero_dirty = true;  // sA / sN / sstamp / ssteps must start zeroed
     bool zero_dirty = true;  // N / aux must be zero between runs
     uint32_t* d_qcount = nullptr;
     uint32_t cap = 0;
@@ -896,11 +896,11 @@ int simulate_sets_impl(ims_graph* g, const uint64_t* base, const uint32_t* set_o
     const int per_cu = opts && opts->blocks_per_cu > 0 ? opts->blocks_per_cu : 2;
     const uint64_t slots = std::min<uint64_t>(tasks, (uint64_t)g->cus * per_cu);
     const uint64_t cells = slots * n;
+    const uint64_t before = g->sA.bytes + g->sN.bytes + g->sstamp.bytes + g->ssteps.bytes;
     if ((rc = ensure_buf(g, g->sA, cells * 8, false))) return rc;
     if ((rc = ensure_buf(g, g->sact, cells * 4, false))) return rc;
     if ((rc = ensure_buf(g, g->sQ[0], cells * 4, false))) return rc;
     if ((rc = ensure_buf(g, g->sQ[1], cells * 4, false))) return rc;
-    const uint64_t before = g->sN.bytes + g->sstamp.bytes + g->ssteps.bytes;
     if (g->model == IMS_MODEL_IC) {
         if ((rc = ensure_buf(g, g->sN, cells * 8, false))) return rc;
         if ((rc = ensure_buf(g, g->sQ[2], cells * 16, false))) return rc;
@@ -909,7 +909,7 @@ int simulate_sets_impl(ims_graph* g, const uint64_t* base, const uint32_t* set_o
         if ((rc = ensure_buf(g, g->sstamp, cells * 4, false))) return rc;
         if ((rc = ensure_buf(g, g->ssteps, slots * 4, false))) return rc;
     }
-    if (g->sN.bytes + g->sstamp.bytes + g->ssteps.bytes != before) g->sets_zero_dirty = true;
+    if (g->sA.bytes + g->sN.bytes + g->sstamp.bytes + g->ssteps.bytes != before) g->sets_zero_dirty = true;
     const uint64_t set_bytes = (off.size() + nodes.size()) * sizeof(uint32_t);
     if ((rc = ensure_buf(g, g->sets_dev, set_bytes, false))) return rc;
     uint32_t* d_off = (uint32_t*)g->sets_dev.p;
@@ -917,10 +917,11 @@ int simulate_sets_impl(ims_graph* g, const uint64_t* base, const uint32_t* set_o
     IMS_HIP(hipMemcpyAsync(d_off, off.data(), off.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
     if (!nodes.empty()) IMS_HIP(hipMemcpyAsync(d_nodes, nodes.data(), nodes.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
 
-    // slot state starts clear; tasks clear what they touch
-    if ((rc = fill_async<uint64_t>((uint64_t*)g->sA.p, cells, 0ull, s))) return rc;
+    // slot state starts clear: fresh buffers are cleared once, and every task
+    // clears what it touched (the rows of the nodes it activated, its next-
+    // step masks; stamps only grow)
     if (g->sets_zero_dirty) {
-        for (ims_graph::Buf* b : {&g->sN, &g->sstamp, &g->ssteps})
+        for (ims_graph::Buf* b : {&g->sA, &g->sN, &g->sstamp, &g->ssteps})
             if (b->p && (rc = fill_async<uint8_t>((uint8_t*)b->p, b->bytes, 0, s))) return rc;
         g->sets_zero_dirty = false;
     }
