@@ -477,9 +477,9 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
     std::sort(sv.begin(), sv.end());
     sv.erase(std::unique(sv.begin(), sv.end()), sv.end());
 
-    const uint32_t W = (n_trials + 63) / 64;
+    uint32_t W = (n_trials + 63) / 64;
     const uint64_t n = (uint64_t)g->n;
-    const uint64_t cells = (uint64_t)W * n;
+    uint64_t cells = (uint64_t)W * n;
     // execution shape: word-local when there are enough words to occupy the
     // device (a word per workgroup, a quarter of the compute units or more);
     // grid-wide steps otherwise, whatever the graph size (measured faster at
@@ -508,6 +508,13 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
             if (rc) return rc;
         }
         return IMS_OK;
+    }
+    // LT grid shape with 9 to 15 words: node-major rows padded to 16 words
+    // (the words past n_trials hold no trial), so that a node's row is one
+    // 128-byte line rather than straddling two
+    if (shape == 2 && g->model == IMS_MODEL_LT && W > 8 && W < imsim::kRowWords) {
+        W = imsim::kRowWords;
+        cells = (uint64_t)W * n;
     }
 
     // word-local runs that return only counts take the slot form: each word

@@ -123,10 +123,15 @@ struct SimParams {
     uint32_t cap;            // step guard
 };
 
+// Trials of word w that exist (T trials in all); words past the last one
+// (a padded state row) hold none.  W is not needed: the count comes from T.
 __device__ __forceinline__ uint64_t valid_mask(uint32_t w, uint32_t W, uint32_t T)
 {
-    const uint32_t tail = T & 63u;
-    return (w + 1 < W || tail == 0) ? ~0ull : ((1ull << tail) - 1ull);
+    (void)W;
+    const uint32_t lo = 64u * w;
+    if (lo >= T) return 0ull;
+    const uint32_t r = T - lo;
+    return r >= 64u ? ~0ull : ((1ull << r) - 1ull);
 }
 
 __device__ __forceinline__ uint64_t load_relaxed(const uint64_t* p)
@@ -2111,7 +2116,7 @@ __global__ __launch_bounds__(kBlock) void ltg_finish_kernel(const uint64_t* __re
             for (uint32_t x = 0; x < kRowWords; ++x) {
                 if (x >= gw) break;
                 c += (uint32_t)__popcll(wd[x]);
-                if (A && ok) A[(uint64_t)(wg + x) * (uint64_t)n + v] = wd[x];
+                if (A && ok && 64u * (wg + x) < T) A[(uint64_t)(wg + x) * (uint64_t)n + v] = wd[x];
                 acc[x] += (uint32_t)__popcll(wave_transpose64(wd[x], lane));
             }
             if (ok && node_counts) node_counts[v] = (wg == 0 && !accumulate ? 0u : node_counts[v]) + c;

@@ -238,6 +238,18 @@ def test_lt_grid_threshold_paths_and_direction_switch(ims, flags, alpha):
     run_both(ims, "lt", g.n, g.offsets, g.indices, param, seeds, 200, 23, opts=opts)
 
 
+@pytest.mark.parametrize("T,flags", [(600, 0), (832, 0), (832, 8), (900, 1), (1600, 0)])
+def test_lt_grid_padded_rows(ims, T, flags):
+    """9 to 15 words of trials (alone, or as the last 16-word run): the
+    node-major rows are padded to 16 words, and the padding holds no trial;
+    every threshold form, bits against the oracle."""
+    g = synth.chung_lu_directed(20000, 2.1, 8.0, seed=35)
+    param = synth.weighted_cascade(g)
+    seeds = synth.top_outdeg_seeds(g, 20)
+    opts = ims.Opts(shape=2, blocks_per_cu=0, alpha=0.0, profile=0, test_flags=flags)
+    run_both(ims, "lt", g.n, g.offsets, g.indices, param, seeds, T, 31, opts=opts)
+
+
 @pytest.mark.parametrize("T", [1025, 1500])
 def test_lt_grid_count_thresholds_over_several_word_groups(ims, T):
     """Count-threshold table and sweep with more than one group of 16 words,
