@@ -511,9 +511,13 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
     }
     // LT grid shape with 9 to 15 words: node-major rows padded to 16 words
     // (the words past n_trials hold no trial), so that a node's row is one
-    // 128-byte line rather than straddling two
+    // 128-byte line rather than straddling two; 6 and 7 words likewise to 8
+    // (measured 3-4% faster; 5 words padded measured 1% slower)
     if (shape == 2 && g->model == IMS_MODEL_LT && W > 8 && W < imsim::kRowWords) {
         W = imsim::kRowWords;
+        cells = (uint64_t)W * n;
+    } else if (shape == 2 && g->model == IMS_MODEL_LT && (W == 6 || W == 7)) {
+        W = 8;
         cells = (uint64_t)W * n;
     }
 

@@ -238,7 +238,7 @@ def test_lt_grid_threshold_paths_and_direction_switch(ims, flags, alpha):
     run_both(ims, "lt", g.n, g.offsets, g.indices, param, seeds, 200, 23, opts=opts)
 
 
-@pytest.mark.parametrize("T,flags", [(600, 0), (832, 0), (832, 8), (900, 1), (1600, 0)])
+@pytest.mark.parametrize("T,flags", [(300, 0), (400, 8), (600, 0), (832, 0), (832, 8), (900, 1), (1600, 0)])
 def test_lt_grid_padded_rows(ims, T, flags):
     """9 to 15 words of trials (alone, or as the last 16-word run): the
     node-major rows are padded to 16 words, and the padding holds no trial;
