@@ -116,6 +116,8 @@ struct ims_graph {
     // sets mode (ims_simulate_sets): per-slot state
     Buf sA, sN, sQ[3], sact, sstamp, ssteps, sets_dev;
     imsim::BatchItem* d_item = nullptr;  // the single-run slot form's item
+    imsim::BatchItem* h_item = nullptr;  // its pinned host staging copy
+    hipEvent_t item_copied = nullptr;    // the last upload of h_item has completed
     bool sets_zero_dirty = true;  // sA / sN / sstamp / ssteps must start zeroed
     bool zero_dirty = true;  // N / aux must be zero between runs
     uint32_t* d_qcount = nullptr;
@@ -167,6 +169,8 @@ struct ims_graph {
         dev_free(d_seed_pre);
         dev_free(d_status);
         if (h_flag) (void)hipHostFree(h_flag);
+        if (h_item) (void)hipHostFree(h_item);
+        if (item_copied) (void)hipEventDestroy(item_copied);
     }
 };
 
@@ -547,6 +551,8 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
             g->sets_zero_dirty = false;
         }
         if (!g->d_item && (rc = dev_alloc(&g->d_item, 1))) return rc;
+        if (!g->h_item) IMS_HIP(hipHostMalloc((void**)&g->h_item, sizeof(imsim::BatchItem), hipHostMallocDefault));
+        if (!g->item_copied) IMS_HIP(hipEventCreateWithFlags(&g->item_copied, hipEventDisableTiming));
     }
     if (!active_bits && !slot_run && (rc = ensure_buf(g, g->A, cells * 8, false))) return rc;
     if (shape == 1 && !slot_run) {
@@ -683,14 +689,18 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
     }
     if (slot_run) {
         if (node_counts && (rc = fill_async<uint32_t>(node_counts, n, 0u, s))) return rc;
-        imsim::BatchItem it;
+        // the item goes up from pinned memory, which the previous call's
+        // upload must have finished reading before it is overwritten
+        IMS_HIP(hipEventSynchronize(g->item_copied));
+        imsim::BatchItem& it = *g->h_item;
         std::memset(&it, 0, sizeof it);
         it.P = P;
         it.model = g->model;
         it.trial_counts = trial_counts;
         it.node_counts = node_counts;
         it.total = total;
-        IMS_HIP(hipMemcpyAsync(g->d_item, &it, sizeof it, hipMemcpyHostToDevice, s));
+        IMS_HIP(hipMemcpyAsync(g->d_item, g->h_item, sizeof it, hipMemcpyHostToDevice, s));
+        IMS_HIP(hipEventRecord(g->item_copied, s));
         imsim::SlotBufs S{n,
                           (uint64_t*)g->sA.p,
                           (uint64_t*)g->sN.p,
