@@ -129,3 +129,82 @@ def test_closed_form_with_zero_weights_and_seed_counting():
     p[R.OFF["bo"]] = -800.0
     pred = R.forward(p, n, off, idx, a, sets)["pred"]
     np.testing.assert_array_equal(pred, [2.0, 0.0, 4.0])
+
+
+def _header_offsets():
+    """Parameter offsets as the C header declares them."""
+    import os
+    import re
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "imsim_mpnn.h")
+    with open(path) as f:
+        return {k: int(v) for k, v in re.findall(r"#define IMS_MPNN_OFF_(\w+) (\d+)", f.read())}
+
+
+def test_forward_by_hand_from_the_header_definition():
+    """Three nodes, arcs 0->1 (a = 1/2), 2->1 (1/4), 1->0 (3/4), nonzero
+    weights everywhere; every layer written out scalar by scalar from the
+    header: z_v[c] = b[c] + sum_k h_v[k] W[k][c] + sum_k m_v[k] W[d + k][c]
+    with m_v = sum over arcs (u, v) of a_uv h_u, W row-major [2d][64] at the
+    header's offsets; readout 1 for seeds, else sigmoid(h_v . w_o + b_o)."""
+    import math
+    off_h = _header_offsets()
+    n = 3
+    offsets = np.array([0, 1, 2, 3], dtype=np.int64)
+    indices = np.array([1, 0, 1], dtype=np.uint32)
+    a = np.array([0.5, 0.75, 0.25], dtype=np.float32)
+    arcs = [(0, 1, 0.5), (1, 0, 0.75), (2, 1, 0.25)]
+    rng = np.random.default_rng(21)
+    params = rng.normal(0.0, 0.3, size=off_h["BO"] + 1)
+    sets = [[0], [2], [0, 2], []]
+
+    outdeg = [1, 1, 1]
+    indeg = [1, 2, 0]
+    asum = [0.5, 0.75, 0.25]
+    f32 = lambda x: float(np.float32(x))  # noqa: E731  (features are stored as float32)
+    widths = [16, 64, 64, 64]
+    preds = []
+    for s in sets:
+        h = [[0.0] * 16 for _ in range(n)]
+        for v in range(n):
+            h[v][0] = 1.0 if v in s else 0.0
+            h[v][1] = f32(math.log1p(outdeg[v]))
+            h[v][2] = f32(math.log1p(indeg[v]))
+            h[v][3] = f32(math.log1p(asum[v]))
+        for layer in range(3):
+            d = widths[layer]
+            wo_, bo_ = off_h[f"W{layer}"], off_h[f"B{layer}"]
+            m = [[0.0] * d for _ in range(n)]
+            for (u, v, w) in arcs:
+                for k in range(d):
+                    m[v][k] += w * h[u][k]
+            nh = [[0.0] * 64 for _ in range(n)]
+            for v in range(n):
+                for c in range(64):
+                    z = params[bo_ + c]
+                    for k in range(d):
+                        z += h[v][k] * params[wo_ + k * 64 + c]          # self rows 0 .. d-1
+                        z += m[v][k] * params[wo_ + (d + k) * 64 + c]    # aggregate rows d .. 2d-1
+                    nh[v][c] = max(z, 0.0)
+            h = nh
+        total = 0.0
+        for v in range(n):
+            if v in s:
+                total += 1.0
+            else:
+                z = params[off_h["BO"]] + sum(h[v][c] * params[off_h["WO"] + c] for c in range(64))
+                total += 1.0 / (1.0 + math.exp(-z))
+        preds.append(total)
+    got = R.forward(params, n, offsets, indices, a, sets)["pred"]
+    np.testing.assert_allclose(got, preds, rtol=1e-12, atol=0)
+    # the offsets of the reference equal the header's
+    for k, v in R.OFF.items():
+        assert off_h[k.upper()] == v
+    assert R.NPARAMS == off_h["BO"] + 1
+    # swapping the self and aggregate halves of any one layer changes the answer
+    for layer in range(3):
+        d = widths[layer]
+        sw = params.copy()
+        base = R.OFF[f"W{layer}"]
+        Wl = sw[base:base + 2 * d * 64].reshape(2 * d, 64).copy()
+        sw[base:base + 2 * d * 64] = np.concatenate([Wl[d:], Wl[:d]]).ravel()
+        assert np.max(np.abs(R.forward(sw, n, offsets, indices, a, sets)["pred"] - preds)) > 1e-6
