@@ -77,8 +77,9 @@ _sig("ims_debug_hash", _int, _u64, _u64, _P, _P, _P, _i64, _P)
 
 
 class ImsError(RuntimeError):
-    def __init__(self, code: int, where: str):
-        msg = _lib.ims_last_error().decode(errors="replace")
+    def __init__(self, code: int, where: str, msg: str | None = None):
+        if msg is None:
+            msg = _lib.ims_last_error().decode(errors="replace")
         super().__init__(f"{where}: {ERRORS.get(code, code)}: {msg}")
         self.code = code
 
@@ -183,16 +184,45 @@ class Graph:
         return int(out[0]), int(out[1])
 
 
+def _dev_ptr(t, where: str, name: str, itemsize: int, numel: int, required: bool = True):
+    """Device address of an output tensor after checking that the library can
+    write `numel` items of `itemsize` bytes there: a CUDA tensor on the
+    current device, contiguous, of that item size, large enough.  The check
+    runs before any device work, so a wrong buffer is an error, not a write
+    out of bounds."""
+    if t is None:
+        if required:
+            raise ImsError(-1, where, f"{name} is required")
+        return None
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ImsError(-1, where, f"{name} must be a CUDA tensor")
+    if t.device.index != torch.cuda.current_device():
+        raise ImsError(-1, where, f"{name} is on {t.device}, not the current device")
+    if not t.is_contiguous():
+        raise ImsError(-1, where, f"{name} must be contiguous")
+    if t.element_size() != itemsize or t.is_floating_point() or t.is_complex():
+        raise ImsError(-1, where, f"{name} must hold {itemsize}-byte integers, not {t.dtype}")
+    if t.numel() < numel:
+        raise ImsError(-1, where, f"{name} holds {t.numel()} items, needs {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
 def simulate_into(graph: Graph, seeds, n_trials: int, rng_seed: int, trial_counts, total,
                   node_counts=None, active_bits=None, stream=None, opts: Opts | None = None) -> None:
     """Enqueue one simulation on `stream` writing into caller tensors."""
     seeds = np.ascontiguousarray(seeds, dtype=np.uint32)
-    ptr = lambda t: None if t is None else ctypes.c_void_p(t.data_ptr())
+    T = int(n_trials)
+    W = (T + 63) // 64
+    where = "ims_simulate"
+    tc = _dev_ptr(trial_counts, where, "trial_counts", 4, T)
+    tot = _dev_ptr(total, where, "total", 8, 1)
+    nc = _dev_ptr(node_counts, where, "node_counts", 4, graph.n, required=False)
+    bits = _dev_ptr(active_bits, where, "active_bits", 8, W * graph.n, required=False)
     _check(_lib.ims_simulate(graph.handle, _np_ptr(seeds) if seeds.size else None, seeds.shape[0],
-                             int(n_trials), int(rng_seed) & ((1 << 64) - 1),
+                             T, int(rng_seed) & ((1 << 64) - 1),
                              ctypes.byref(opts) if opts is not None else None,
-                             ptr(trial_counts), ptr(node_counts), ptr(total), ptr(active_bits),
-                             _stream_handle(stream)), "ims_simulate")
+                             tc, nc, tot, bits, _stream_handle(stream)), where)
 
 
 def simulate(graph: Graph, seeds, n_trials: int, rng_seed: int, want_bits: bool = False,
@@ -257,11 +287,13 @@ def simulate_sets_into(graph: Graph, offsets: np.ndarray, nodes: np.ndarray, n_t
                        totals, node_counts=None, stream=None, opts: Opts | None = None) -> None:
     """Enqueue the simulation of many seed sets (common random numbers)."""
     n_sets = int(offsets.shape[0]) - 1
-    ptr = lambda t: None if t is None else ctypes.c_void_p(t.data_ptr())
+    where = "ims_simulate_sets"
+    tot = _dev_ptr(totals, where, "totals", 8, n_sets)
+    nc = _dev_ptr(node_counts, where, "node_counts", 4, n_sets * graph.n, required=False)
     _check(_lib.ims_simulate_sets(graph.handle, _np_ptr(offsets), _np_ptr(nodes) if nodes.size else None, n_sets,
                                   int(n_trials), int(rng_seed) & ((1 << 64) - 1),
                                   ctypes.byref(opts) if opts is not None else None,
-                                  ptr(totals), ptr(node_counts), _stream_handle(stream)), "ims_simulate_sets")
+                                  tot, nc, _stream_handle(stream)), where)
 
 
 def simulate_sets(graph: Graph, sets, n_trials: int, rng_seed: int, want_node_counts: bool = False,
@@ -288,11 +320,15 @@ def simulate_sets_from_into(graph: Graph, base_bits, offsets: np.ndarray, nodes:
     base_bits ([W, n] active bits of a run with the same n_trials and
     rng_seed); totals receive the new activations only."""
     n_sets = int(offsets.shape[0]) - 1
-    ptr = lambda t: None if t is None else ctypes.c_void_p(t.data_ptr())
-    _check(_lib.ims_simulate_sets_from(graph.handle, ptr(base_bits), _np_ptr(offsets), _np_ptr(nodes) if nodes.size else None,
+    where = "ims_simulate_sets_from"
+    W = (int(n_trials) + 63) // 64
+    base = _dev_ptr(base_bits, where, "base_bits", 8, W * graph.n)
+    tot = _dev_ptr(totals, where, "totals", 8, n_sets)
+    nc = _dev_ptr(node_counts, where, "node_counts", 4, n_sets * graph.n, required=False)
+    _check(_lib.ims_simulate_sets_from(graph.handle, base, _np_ptr(offsets), _np_ptr(nodes) if nodes.size else None,
                                        n_sets, int(n_trials), int(rng_seed) & ((1 << 64) - 1),
-                                       ctypes.byref(opts) if opts is not None else None, ptr(totals), ptr(node_counts),
-                                       _stream_handle(stream)), "ims_simulate_sets_from")
+                                       ctypes.byref(opts) if opts is not None else None, tot, nc,
+                                       _stream_handle(stream)), where)
 
 
 def simulate_sets_from(graph: Graph, base_bits, sets, n_trials: int, rng_seed: int, want_node_counts: bool = False,

@@ -76,3 +76,34 @@ def test_graph_create_rejects_before_touching_the_device():
     with pytest.raises(ims.ImsError) as e:
         ims.Graph(3, off, idx, "ic", np.array([0.1, 2.0, 0.1]))
     assert e.value.code == -1
+
+
+def test_output_buffers_checked_before_any_device_call():
+    """The binding rejects outputs the library could not write safely (host
+    tensors, wrong item size, too small, not contiguous, missing) before it
+    touches the device; a stand-in graph object is enough since nothing
+    reaches the library."""
+    import types
+
+    import torch
+    g = types.SimpleNamespace(n=10, handle=None)
+    cases = [
+        dict(trial_counts=torch.zeros(5, dtype=torch.int32), total=torch.zeros(1, dtype=torch.int64)),
+        dict(trial_counts=None, total=torch.zeros(1, dtype=torch.int64)),
+    ]
+    for kw in cases:
+        with pytest.raises(ims.ImsError) as e:
+            ims.simulate_into(g, [0], 5, 1, **kw)
+        assert e.value.code == -1
+    with pytest.raises(ims.ImsError):
+        ims.simulate_sets_into(g, np.array([0, 1], dtype=np.uint32), np.array([0], dtype=np.uint32), 5, 1,
+                               torch.zeros(1, dtype=torch.int64))
+    with pytest.raises(ims.ImsError):
+        ims.simulate_sets_from_into(g, torch.zeros(10, dtype=torch.int64), np.array([0, 1], dtype=np.uint32),
+                                    np.array([0], dtype=np.uint32), 5, 1, torch.zeros(1, dtype=torch.int64))
+    # the checks themselves, without a GPU (only the host-tensor rule applies here)
+    with pytest.raises(ims.ImsError, match="CUDA tensor"):
+        ims._dev_ptr(torch.zeros(4, dtype=torch.int32), "w", "x", 4, 4)
+    with pytest.raises(ims.ImsError, match="required"):
+        ims._dev_ptr(None, "w", "x", 4, 4)
+    assert ims._dev_ptr(None, "w", "x", 4, 4, required=False) is None
