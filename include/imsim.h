@@ -142,6 +142,30 @@ int ims_simulate_levels(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, u
                         uint32_t max_levels, uint32_t* level_counts, uint32_t* trial_counts, uint64_t* total,
                         void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the run of
+ * ims_simulate in its count-only word-local form (each 64-trial word as four
+ * 16-trial tasks on persistent workgroup slots), with every per-call device
+ * buffer (slot state, seed list, task counter) taken from one fixed device
+ * array of IMS_NOALLOC_SCRATCH_BYTES per GPU, which the library holds from its
+ * first use on that GPU until the process ends.  It calls no allocator.
+ *   Arguments as ims_simulate (host seeds, duplicates allowed, ids < n;
+ *   device outputs trial_counts uint32[T] and total uint64[1] required,
+ *   node_counts uint32[n] optional); results are identical to ims_simulate's.
+ *   The graph must live on the current device.
+ *   Limit: the array must hold about 1 KiB + 8 B per seed + 4 B per node plus
+ *   one workgroup slot of 48 B per node (so about 1.39M nodes at most);
+ *   larger requests fail with IMS_E_UNSUPPORTED.  Smaller graphs get more
+ *   slots (up to two per compute unit), so throughput drops only for large n.
+ *   Every call on one GPU shares that GPU's array and clears what it needs at
+ *   its start: calls that overlap in time on one GPU (other streams, other
+ *   threads) race and give wrong results.  Asynchronous on `stream`; the
+ *   seeds travel as kernel arguments, so they are read during the call only.
+ *   ims_graph_last_status reports the run's steps and step guard as usual. */
+#define IMS_NOALLOC_SCRATCH_BYTES (64u << 20)
+int ims_simulate_noalloc(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_t n_trials, uint64_t rng_seed,
+                         uint32_t* trial_counts, uint32_t* node_counts, uint64_t* total, void* stream);
+
 /* Many seed sets on one graph with common random numbers (every set sees the
  * same coins / thresholds: same rng_seed and trials 0 .. n_trials-1), as the
  * greedy and CELF influence maximisation of Section 2 evaluate sigma(S + v)

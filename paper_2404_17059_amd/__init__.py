@@ -74,6 +74,9 @@ _sig("ims_simulate_levels", _int, _P, _P, _u32, _u32, _u64, _u32, _P, _P, _P, _P
 _sig("ims_simulate_sets_from", _int, _P, _P, _P, _P, _u32, _u32, _u64, ctypes.POINTER(Opts), _P, _P, _P)
 _sig("ims_graph_profile", _int, _P, _int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_u32))
 _sig("ims_debug_hash", _int, _u64, _u64, _P, _P, _P, _i64, _P)
+_sig("ims_simulate_noalloc", _int, _P, _P, _u32, _u32, _u64, _P, _P, _P, _P)
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # IMS_NOALLOC_SCRATCH_BYTES of include/imsim.h
 
 
 class ImsError(RuntimeError):
@@ -223,6 +226,21 @@ def simulate_into(graph: Graph, seeds, n_trials: int, rng_seed: int, trial_count
                              T, int(rng_seed) & ((1 << 64) - 1),
                              ctypes.byref(opts) if opts is not None else None,
                              tc, nc, tot, bits, _stream_handle(stream)), where)
+
+
+def simulate_noalloc_into(graph: Graph, seeds, n_trials: int, rng_seed: int, trial_counts, total,
+                          node_counts=None, stream=None) -> None:
+    """Enqueue one counts-only simulation through the allocation-free entry
+    point (its device state lives in the library's fixed per-GPU array;
+    overlapping calls on one GPU race)."""
+    seeds = np.ascontiguousarray(seeds, dtype=np.uint32)
+    T = int(n_trials)
+    where = "ims_simulate_noalloc"
+    tc = _dev_ptr(trial_counts, where, "trial_counts", 4, T)
+    tot = _dev_ptr(total, where, "total", 8, 1)
+    nc = _dev_ptr(node_counts, where, "node_counts", 4, graph.n, required=False)
+    _check(_lib.ims_simulate_noalloc(graph.handle, _np_ptr(seeds) if seeds.size else None, seeds.shape[0],
+                                     T, int(rng_seed) & ((1 << 64) - 1), tc, nc, tot, _stream_handle(stream)), where)
 
 
 def simulate(graph: Graph, seeds, n_trials: int, rng_seed: int, want_bits: bool = False,

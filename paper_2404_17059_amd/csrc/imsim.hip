@@ -12,6 +12,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1317,6 +1318,229 @@ int ims_debug_hash(uint64_t rng_seed, uint64_t domain, const uint64_t* trials, c
     hipLaunchKernelGGL(imsim::debug_hash_kernel, dim3((unsigned)blocks), dim3(imsim::kBlock), 0, (hipStream_t)stream, rng_seed, domain,
                        trials, ids, out, count);
     IMS_HIP(hipGetLastError());
+    return IMS_OK;
+}
+
+}  // extern "C"
+
+// ============================================ allocation-free single run
+//
+// ims_simulate_noalloc runs the count-only word-local form of ims_simulate
+// (slot_run_kernel: each 64-trial word as four 16-trial tasks on persistent
+// workgroup slots) with every per-call device buffer carved out of one fixed
+// device array, `scratch`, instead of the graph's growing workspace.  The
+// graph handle (created beforehand) and the caller's outputs are the only
+// other device memory it touches; it calls no allocator.
+
+namespace {
+
+constexpr uint64_t kNoAllocBytes = (uint64_t)IMS_NOALLOC_SCRATCH_BYTES;
+constexpr uint32_t kSeedChunk = 512;  // seeds carried by one upload launch's arguments
+constexpr int kMaxDevices = 64;
+
+}  // namespace
+
+// One copy per GPU, resident from the library's load on that GPU until the
+// process ends.  Host code never names it except to ask for its address.
+static __device__ __align__(256) uint8_t scratch[IMS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device `dev` (current), looked up once per
+// device; the array's host-side name is not a device address.
+int scratch_address(int dev, uint8_t** out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(IMS_E_UNSUPPORTED, "ims_simulate_noalloc: device %d above %d", dev, kMaxDevices - 1);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(IMS_E_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = (uint8_t*)g_scratch_ptr[dev];
+    return IMS_OK;
+}
+
+struct SeedChunk {
+    uint32_t first;
+    uint32_t count;
+    uint32_t v[kSeedChunk];
+};
+
+// Seeds reach the device through kernel arguments (copied at launch), so the
+// caller's host array is read only during the call, whatever memory it is.
+__global__ __launch_bounds__(kSeedChunk) void noalloc_put_seeds_kernel(SeedChunk c, uint32_t* __restrict__ raw)
+{
+    if (threadIdx.x < c.count) raw[c.first + threadIdx.x] = c.v[threadIdx.x];
+}
+
+__global__ __launch_bounds__(64) void noalloc_put_item_kernel(imsim::BatchItem it, imsim::BatchItem* __restrict__ dst)
+{
+    if (threadIdx.x == 0) *dst = it;
+}
+
+// Set semantics on the device: the first position of every seed id wins
+// (mark[] starts at 0xFFFFFFFF) ...
+__global__ __launch_bounds__(imsim::kBlock) void noalloc_seed_first_kernel(const uint32_t* __restrict__ raw, uint32_t count,
+                                                                          uint32_t* __restrict__ mark)
+{
+    for (uint32_t i = blockIdx.x * imsim::kBlock + threadIdx.x; i < count; i += gridDim.x * imsim::kBlock) atomicMin(&mark[raw[i]], i);
+}
+
+// ... and only winners are listed; their count lands in the item's n_seeds
+// (the list order does not matter: every trial's final set is fixed).
+__global__ __launch_bounds__(imsim::kBlock) void noalloc_seed_list_kernel(const uint32_t* __restrict__ raw, uint32_t count,
+                                                                         const uint32_t* __restrict__ mark, uint32_t* __restrict__ seeds,
+                                                                         uint32_t* __restrict__ n_out)
+{
+    for (uint32_t i = blockIdx.x * imsim::kBlock + threadIdx.x; i < count; i += gridDim.x * imsim::kBlock) {
+        const uint32_t v = raw[i];
+        if (mark[v] == i) seeds[atomicAdd(n_out, 1u)] = v;
+    }
+}
+
+uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
+
+// Byte layout of `scratch` for one call.
+struct NoAllocLayout {
+    uint64_t item, counter, raw, seeds, mark, steps, sA, sN, sstamp, zero_end, sQ0, sQ1, sQ2, sact, end;
+};
+
+NoAllocLayout noalloc_layout(uint64_t n, uint64_t n_seeds, uint64_t slots)
+{
+    NoAllocLayout L;
+    L.item = 0;
+    L.counter = align256(sizeof(imsim::BatchItem));
+    L.raw = L.counter + 256;
+    L.seeds = L.raw + align256(4 * n_seeds);
+    L.mark = L.seeds + align256(4 * n_seeds);
+    L.steps = L.mark + align256(4 * n);
+    // slot step counters, active rows, next-step masks and stamps must start
+    // at zero: they are laid out together and cleared as one range
+    L.sA = L.steps + align256(4 * slots);
+    L.sN = L.sA + align256(8 * slots * n);
+    L.sstamp = L.sN + align256(8 * slots * n);
+    L.zero_end = L.sstamp + align256(4 * slots * n);
+    L.sQ0 = L.zero_end;
+    L.sQ1 = L.sQ0 + align256(4 * slots * n);
+    L.sQ2 = L.sQ1 + align256(4 * slots * n);
+    L.sact = L.sQ2 + align256(16 * slots * n);
+    L.end = L.sact + align256(4 * slots * n);
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ims_simulate_noalloc(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_t n_trials, uint64_t rng_seed,
+                         uint32_t* trial_counts, uint32_t* node_counts, uint64_t* total, void* stream)
+{
+    if (!g) return fail(IMS_E_INVALID_ARG, "ims_simulate_noalloc: NULL graph");
+    if (n_trials == 0) return fail(IMS_E_INVALID_ARG, "ims_simulate_noalloc: n_trials must be >= 1");
+    if (n_trials > imsim::kMaxWords * 64u)
+        return fail(IMS_E_UNSUPPORTED, "ims_simulate_noalloc: n_trials above %u", imsim::kMaxWords * 64u);
+    if (!trial_counts || !total) return fail(IMS_E_INVALID_ARG, "ims_simulate_noalloc: trial_counts and total are required");
+    if (n_seeds > 0 && !seeds) return fail(IMS_E_INVALID_ARG, "ims_simulate_noalloc: seeds is NULL");
+    for (uint32_t i = 0; i < n_seeds; ++i)
+        if ((int64_t)seeds[i] >= g->n) return fail(IMS_E_SEED_RANGE, "seed %u >= n = %lld", seeds[i], (long long)g->n);
+    int dev = -1;
+    IMS_HIP(hipGetDevice(&dev));
+    if (dev != g->device) return fail(IMS_E_INVALID_ARG, "ims_simulate_noalloc: current device %d, graph on device %d", dev, g->device);
+    int rc = device_cus(g);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const uint64_t n = (uint64_t)g->n;
+    const uint32_t W = (n_trials + 63) / 64;
+    const uint32_t sp = 2;  // four 16-trial tasks per word, as the counts-only form of ims_simulate
+    const uint64_t tasks = (uint64_t)W << sp;
+    // as many slots as fit, up to two workgroups per compute unit
+    uint64_t slots = std::min<uint64_t>(tasks, (uint64_t)g->cus * 2);
+    while (slots > 0 && noalloc_layout(n, n_seeds, slots).end > kNoAllocBytes) slots = slots > 8 ? slots - slots / 8 : slots - 1;
+    if (slots == 0)
+        return fail(IMS_E_UNSUPPORTED,
+                    "ims_simulate_noalloc: %lld nodes and %u seeds need %llu bytes of scratch for one workgroup slot, above the "
+                    "fixed %llu (about 48 bytes per node plus 8 per seed)",
+                    (long long)g->n, n_seeds, (unsigned long long)noalloc_layout(n, n_seeds, 1).end,
+                    (unsigned long long)kNoAllocBytes);
+    const NoAllocLayout L = noalloc_layout(n, n_seeds, slots);
+    uint8_t* base = nullptr;
+    if ((rc = scratch_address(dev, &base))) return rc;
+
+    // clear what must start at zero (fill kernels, no memset nodes)
+    if ((rc = fill_async<uint64_t>((uint64_t*)(base + L.counter), 256 / 8, 0ull, s))) return rc;
+    if ((rc = fill_async<uint32_t>((uint32_t*)(base + L.mark), n, 0xFFFFFFFFu, s))) return rc;
+    if ((rc = fill_async<uint64_t>((uint64_t*)(base + L.steps), (L.zero_end - L.steps) / 8, 0ull, s))) return rc;
+    if ((rc = fill_async<uint32_t>(g->d_status, 4, 0u, s))) return rc;
+    if ((rc = fill_async<uint32_t>(trial_counts, n_trials, 0u, s))) return rc;
+    if ((rc = fill_async<unsigned long long>((unsigned long long*)total, 1, 0ull, s))) return rc;
+    if (node_counts && (rc = fill_async<uint32_t>(node_counts, n, 0u, s))) return rc;
+
+    // the item: graph, run parameters and outputs; n_seeds is counted below
+    imsim::BatchItem it;
+    std::memset(&it, 0, sizeof it);
+    imsim::SimParams& P = it.P;
+    P.n = g->n;
+    P.T = n_trials;
+    P.W = W;
+    P.seed = rng_seed;
+    P.off = g->d_off;
+    P.idx = g->d_idx;
+    P.thr = g->d_thr;
+    P.in_off = g->d_in_off;
+    P.in_arc = g->d_in_arc;
+    P.in_src32 = g->d_in_src32;
+    P.node_w = g->d_node_w;
+    P.lt_uniform = g->lt_uniform ? 1 : 0;
+    P.seeds = (const uint32_t*)(base + L.seeds);
+    P.n_seeds = 0;
+    P.cap = g->cap;
+    it.model = g->model;
+    it.trial_counts = trial_counts;
+    it.node_counts = node_counts;
+    it.total = total;
+    imsim::BatchItem* d_item = (imsim::BatchItem*)(base + L.item);
+    hipLaunchKernelGGL(noalloc_put_item_kernel, dim3(1), dim3(64), 0, s, it, d_item);
+    IMS_HIP(hipGetLastError());
+
+    uint32_t* raw = (uint32_t*)(base + L.raw);
+    for (uint32_t first = 0; first < n_seeds; first += kSeedChunk) {
+        SeedChunk c;
+        c.first = first;
+        c.count = std::min<uint32_t>(kSeedChunk, n_seeds - first);
+        std::memcpy(c.v, seeds + first, c.count * sizeof(uint32_t));
+        hipLaunchKernelGGL(noalloc_put_seeds_kernel, dim3(1), dim3(kSeedChunk), 0, s, c, raw);
+        IMS_HIP(hipGetLastError());
+    }
+    if (n_seeds > 0) {
+        const uint32_t blocks = std::min<uint32_t>((n_seeds + imsim::kBlock - 1) / imsim::kBlock, 1024);
+        uint32_t* mark = (uint32_t*)(base + L.mark);
+        hipLaunchKernelGGL(noalloc_seed_first_kernel, dim3(blocks), dim3(imsim::kBlock), 0, s, (const uint32_t*)raw, n_seeds, mark);
+        hipLaunchKernelGGL(noalloc_seed_list_kernel, dim3(blocks), dim3(imsim::kBlock), 0, s, (const uint32_t*)raw, n_seeds,
+                           (const uint32_t*)mark, (uint32_t*)(base + L.seeds), &d_item->P.n_seeds);
+        IMS_HIP(hipGetLastError());
+    }
+
+    imsim::SlotBufs S{n,
+                      (uint64_t*)(base + L.sA),
+                      (uint64_t*)(base + L.sN),
+                      (uint32_t*)(base + L.sQ0),
+                      (uint32_t*)(base + L.sQ1),
+                      (uint64_t*)(base + L.sQ2),
+                      (uint32_t*)(base + L.sact),
+                      (uint32_t*)(base + L.sstamp),
+                      (uint32_t*)(base + L.steps)};
+    hipLaunchKernelGGL(imsim::slot_run_kernel, dim3((uint32_t)slots), dim3(imsim::kTaskBlock), 0, s, (const imsim::BatchItem*)d_item,
+                       sp, (uint32_t)tasks, (uint32_t*)(base + L.counter), S, g->d_status);
+    IMS_HIP(hipGetLastError());
+    g->last_shape = 1;
     return IMS_OK;
 }
 

@@ -92,9 +92,10 @@ def test_output_buffers_checked_before_any_device_call():
         dict(trial_counts=None, total=torch.zeros(1, dtype=torch.int64)),
     ]
     for kw in cases:
-        with pytest.raises(ims.ImsError) as e:
-            ims.simulate_into(g, [0], 5, 1, **kw)
-        assert e.value.code == -1
+        for fn in (ims.simulate_into, ims.simulate_noalloc_into):
+            with pytest.raises(ims.ImsError) as e:
+                fn(g, [0], 5, 1, **kw)
+            assert e.value.code == -1
     with pytest.raises(ims.ImsError):
         ims.simulate_sets_into(g, np.array([0, 1], dtype=np.uint32), np.array([0], dtype=np.uint32), 5, 1,
                                torch.zeros(1, dtype=torch.int64))
