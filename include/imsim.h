@@ -108,6 +108,20 @@ typedef struct ims_opts {
                               threshold table (hashes drawn in the kernel); bit 1 = unused;
                               bit 2 = LT without the equal-in-weights form; bit 3 = LT grid
                               shape with full threshold hashes instead of count thresholds */
+    /* IC direction (Section 3, "Algorithms", expands the out-arcs of the last
+       step's new nodes: the push side).  The pull side instead lets every
+       (node, word) pair with an inactive trial scan its in-arcs for frontier
+       sources, drawing each arc's coin by its out-CSR id, and stop when its
+       pending trials have all joined.  Per level, by Beamer's rule over the
+       pairs of all words (word-local tasks: over the task's own nodes):
+       push -> pull when the frontier's out-arcs times ic_alpha * pbar exceed
+       the in-arcs of pairs with an inactive trial, where pbar is the mean
+       firing probability of the graph's arcs (a pulled node stops early only
+       as often as its arcs fire); pull -> push when the frontier's pairs
+       times ic_beta fall below W * n (word-local: below n). */
+    double ic_alpha;       /* 0 = 14 */
+    double ic_beta;        /* 0 = 24 */
+    int32_t ic_direction;  /* 0 = by the rule, 1 = push only, 2 = pull only */
 } ims_opts;
 
 /* Run trials 0 .. n_trials-1 from one seed set (Section 2).
@@ -229,14 +243,20 @@ typedef struct ims_tuning {
                                trials and runs their cascade alone, so a split shortens the
                                longest task at the cost of more, smaller tasks; results do not
                                change */
+    double ic_alpha;        /* IC tasks' push -> pull switch point (ims_opts.ic_alpha), 0 = 14 */
+    double ic_beta;         /* IC tasks' pull -> push switch point (ims_opts.ic_beta), 0 = 24 */
 } ims_tuning;
 
-/* tuning NULL = defaults (2 per CU, largest first, 8 tasks per word).  Synchronous. */
+/* tuning NULL = defaults (2 per CU, largest first, 8 tasks per word, default
+ * switch points).  Synchronous. */
 int ims_batch_create(const ims_batch_item* items, uint32_t n_items, const ims_tuning* tuning, ims_batch** out);
-/* Time every candidate schedule (workgroups per compute unit, order, split)
- * `repeats` times on `stream`, check that all give identical outputs, keep
- * the fastest (reported in *chosen if not NULL) and drop the captured graph.
- * Synchronous. */
+/* Time candidate schedules `repeats` times each on `stream`: first
+ * (workgroups per compute unit, order, split) at the default switch points,
+ * then the IC push / pull switch points (alpha; a tiny alpha keeps every task
+ * on the push side) for the fastest of those.  Check that every candidate
+ * gives identical outputs (every item's trial counts, node counts and total;
+ * IMS_E_HIP otherwise), keep the fastest (reported in *chosen if not NULL)
+ * and drop the captured graph.  Synchronous. */
 int ims_batch_autotune(ims_batch* b, int repeats, void* stream, ims_tuning* chosen);
 /* Run the batch on `stream`: the first call (and the first after a tuning
  * change) captures the launch sequence into a HIP graph, later calls replay
@@ -248,6 +268,19 @@ int ims_batch_destroy(ims_batch* b);
  * or LT sweeps) taken, out[1] = nonzero if the step guard fired.  Waits for
  * `stream`. */
 int ims_graph_last_status(ims_graph* g, void* stream, uint32_t out[2]);
+
+/* All four status words of the last run on this handle: out[0], out[1] as
+ * ims_graph_last_status; out[2] = tasks taken (word-local forms); out[3] =
+ * times a word-local step found its 64 workgroup-wide walks of nodes with
+ * more than 512 out-arcs taken and had a wavefront walk one more alone.
+ * Waits for `stream`.  Inspection hook for tests. */
+int ims_graph_last_counters(ims_graph* g, void* stream, uint32_t out[4]);
+
+/* Directions taken by the last IC run of the grid shape on this handle, one
+ * per expanded level: dirs[l] = 1 (push) or 2 (pull), for at most max_levels
+ * levels (host array); *count = levels written (0 after any other kind of
+ * run).  Waits for `stream`.  Inspection hook for tests and profiles. */
+int ims_graph_level_directions(ims_graph* g, uint32_t max_levels, uint32_t* dirs, uint32_t* count, void* stream);
 
 /* Kernel timing of runs made with opts->profile set: waits for the last such
  * run, then returns the summed duration (ms) of the simulation kernel over the

@@ -35,7 +35,8 @@ _i64, _u64, _u32, _int = ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32, ctype
 
 class Opts(ctypes.Structure):
     _fields_ = [("shape", ctypes.c_int), ("blocks_per_cu", ctypes.c_int32), ("alpha", ctypes.c_double),
-                ("profile", ctypes.c_int32), ("test_flags", ctypes.c_int32)]
+                ("profile", ctypes.c_int32), ("test_flags", ctypes.c_int32), ("ic_alpha", ctypes.c_double),
+                ("ic_beta", ctypes.c_double), ("ic_direction", ctypes.c_int32)]
 
 
 class BatchItem(ctypes.Structure):
@@ -45,7 +46,8 @@ class BatchItem(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("blocks_per_cu", ctypes.c_int32), ("order", ctypes.c_int32), ("split", ctypes.c_int32)]
+    _fields_ = [("blocks_per_cu", ctypes.c_int32), ("order", ctypes.c_int32), ("split", ctypes.c_int32),
+                ("ic_alpha", ctypes.c_double), ("ic_beta", ctypes.c_double)]
 
 
 def _sig(name, res, *args):
@@ -73,6 +75,8 @@ _sig("ims_simulate_sets", _int, _P, _P, _P, _u32, _u32, _u64, ctypes.POINTER(Opt
 _sig("ims_simulate_levels", _int, _P, _P, _u32, _u32, _u64, _u32, _P, _P, _P, _P)
 _sig("ims_simulate_sets_from", _int, _P, _P, _P, _P, _u32, _u32, _u64, ctypes.POINTER(Opts), _P, _P, _P)
 _sig("ims_graph_profile", _int, _P, _int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_u32))
+_sig("ims_graph_level_directions", _int, _P, _u32, _P, ctypes.POINTER(_u32), _P)
+_sig("ims_graph_last_counters", _int, _P, _P, _P)
 _sig("ims_debug_hash", _int, _u64, _u64, _P, _P, _P, _i64, _P)
 _sig("ims_simulate_noalloc", _int, _P, _P, _u32, _u32, _u64, _P, _P, _P, _P)
 
@@ -180,6 +184,20 @@ class Graph:
         cnt = ctypes.c_uint32()
         _check(_lib.ims_graph_profile(self._h, int(reset), ctypes.byref(ms), ctypes.byref(cnt)), "ims_graph_profile")
         return float(ms.value), int(cnt.value)
+
+    def level_directions(self, max_levels: int = 4096, stream=None) -> np.ndarray:
+        """Per level of the last IC grid-shape run: 1 = push, 2 = pull."""
+        out = np.zeros(max(int(max_levels), 1), dtype=np.uint32)
+        cnt = ctypes.c_uint32()
+        _check(_lib.ims_graph_level_directions(self._h, int(max_levels), _np_ptr(out), ctypes.byref(cnt),
+                                               _stream_handle(stream)), "ims_graph_level_directions")
+        return out[:cnt.value]
+
+    def last_counters(self, stream=None) -> np.ndarray:
+        """The last run's four status words: steps, guard, tasks taken, hand-overs refused."""
+        out = np.zeros(4, dtype=np.uint32)
+        _check(_lib.ims_graph_last_counters(self._h, _stream_handle(stream), _np_ptr(out)), "ims_graph_last_counters")
+        return out
 
     def last_status(self, stream=None) -> tuple[int, int]:
         out = np.zeros(2, dtype=np.uint32)
@@ -371,7 +389,7 @@ class Batch:
     persistent launch; the first launch captures a HIP graph that later
     launches replay.  items: (Graph, seeds, n_trials, rng_seed) tuples."""
 
-    def __init__(self, items, tuning: tuple[int, int, int] | None = None, want_node_counts: bool = True):
+    def __init__(self, items, tuning: tuple | None = None, want_node_counts: bool = True):
         torch = _torch()
         dev = torch.device("cuda", torch.cuda.current_device())
         self.graphs = [it[0] for it in items]
@@ -394,11 +412,11 @@ class Batch:
                "ims_batch_create")
         self._h = h
 
-    def autotune(self, repeats: int = 2, stream=None) -> tuple[int, int, int]:
-        """Returns the chosen (blocks_per_cu, order, split)."""
+    def autotune(self, repeats: int = 2, stream=None) -> tuple:
+        """Returns the chosen (blocks_per_cu, order, split, ic_alpha, ic_beta)."""
         t = Tuning()
         _check(_lib.ims_batch_autotune(self._h, int(repeats), _stream_handle(stream), ctypes.byref(t)), "ims_batch_autotune")
-        return int(t.blocks_per_cu), int(t.order), int(t.split)
+        return int(t.blocks_per_cu), int(t.order), int(t.split), float(t.ic_alpha), float(t.ic_beta)
 
     def launch(self, stream=None) -> None:
         _check(_lib.ims_batch_launch(self._h, _stream_handle(stream)), "ims_batch_launch")

@@ -96,8 +96,14 @@ struct ims_graph {
     int64_t* d_off = nullptr;
     uint32_t* d_idx = nullptr;
     uint32_t* d_thr = nullptr;
-    int64_t* d_in_off = nullptr;
+    int64_t* d_in_off = nullptr;     // in-CSR offsets (LT: weight pieces; IC: arcs of nonzero threshold)
     uint64_t* d_in_arc = nullptr;  // (source | weight piece << 32) per in-arc
+    uint64_t* d_ic_in = nullptr;     // IC: (source | out-CSR arc id << 32) per in-arc
+    uint32_t* d_ic_in_thr = nullptr; // IC: threshold per in-arc
+    int64_t ic_in_m = 0;             // IC: in-arcs (arcs whose threshold is not 0)
+    double ic_pbar = 0.0;            // IC: mean firing probability of those arcs
+    uint64_t* d_lvl = nullptr;       // IC grid shape: per level frontier out-arcs [cap], full-pair in-arcs [cap]
+    uint32_t* d_lvl_dir = nullptr;   // IC grid shape: direction of each level [cap]
     uint32_t* d_in_src32 = nullptr;  // source per in-arc (uniform-weight form)
     uint32_t* d_node_w = nullptr;    // common weight piece per node (uniform-weight form)
     bool lt_uniform = false;
@@ -159,6 +165,10 @@ struct ims_graph {
         dev_free(d_thr);
         dev_free(d_in_off);
         dev_free(d_in_arc);
+        dev_free(d_ic_in);
+        dev_free(d_ic_in_thr);
+        dev_free(d_lvl);
+        dev_free(d_lvl_dir);
         dev_free(d_in_src32);
         dev_free(d_node_w);
         dev_free(d_bfirst);
@@ -324,6 +334,37 @@ int ims_graph_create(int64_t n, int64_t m, const int64_t* offsets, const uint32_
         if ((rc = dev_alloc(&g->d_thr, (uint64_t)m))) return bail(rc);
         if (m > 0 && hipMemcpy(g->d_thr, param, sizeof(uint32_t) * m, hipMemcpyHostToDevice) != hipSuccess)
             return bail(fail(IMS_E_HIP, "threshold upload failed"));
+        // pull side: for every node its in-arcs in out-CSR order, each with
+        // its source and its out-CSR id (coins are keyed by that id, so a
+        // pulled arc draws the coin its push would) and threshold; arcs with
+        // threshold 0 never fire and are left out
+        const uint32_t* thr = (const uint32_t*)param;
+        std::vector<int64_t> ioff((size_t)n + 1, 0);
+        for (int64_t e = 0; e < m; ++e)
+            if (thr[e] != 0) ++ioff[(size_t)indices[e] + 1];
+        for (int64_t v = 0; v < n; ++v) ioff[v + 1] += ioff[v];
+        const int64_t mi = ioff[n];
+        std::vector<uint64_t> isa((size_t)std::max<int64_t>(mi, 1));
+        std::vector<uint32_t> ithr((size_t)std::max<int64_t>(mi, 1));
+        std::vector<int64_t> pos(ioff.begin(), ioff.end() - 1);
+        for (int64_t u = 0; u < n; ++u)
+            for (int64_t e = offsets[u]; e < offsets[u + 1]; ++e) {
+                if (thr[e] == 0) continue;
+                const int64_t k = pos[indices[e]]++;
+                isa[k] = (uint64_t)u | ((uint64_t)e << 32);
+                ithr[k] = thr[e];
+            }
+        g->ic_in_m = mi;
+        double psum = 0.0;
+        for (int64_t k = 0; k < mi; ++k) psum += ithr[k] == 0xFFFFFFFFu ? 1.0 : std::ldexp((double)ithr[k], -32);
+        g->ic_pbar = mi > 0 ? psum / (double)mi : 0.0;
+        if ((rc = dev_alloc(&g->d_in_off, (uint64_t)n + 1)) || (rc = dev_alloc(&g->d_ic_in, (uint64_t)mi)) ||
+            (rc = dev_alloc(&g->d_ic_in_thr, (uint64_t)mi)))
+            return bail(rc);
+        if (hipMemcpy(g->d_in_off, ioff.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice) != hipSuccess ||
+            (mi > 0 && (hipMemcpy(g->d_ic_in, isa.data(), sizeof(uint64_t) * mi, hipMemcpyHostToDevice) != hipSuccess ||
+                        hipMemcpy(g->d_ic_in_thr, ithr.data(), sizeof(uint32_t) * mi, hipMemcpyHostToDevice) != hipSuccess)))
+            return bail(fail(IMS_E_HIP, "IC in-CSR upload failed"));
     } else {
         const int64_t mi = in_off[n];
         if ((rc = dev_alloc(&g->d_in_off, (uint64_t)n + 1))) return bail(rc);
@@ -419,6 +460,8 @@ int ims_graph_create(int64_t n, int64_t m, const int64_t* offsets, const uint32_
     }
     g->cap = (uint32_t)std::min<int64_t>(n + 8, 0xFFFFFFF0ll);
     if ((rc = dev_alloc(&g->d_qcount, g->cap))) return bail(rc);
+    if (model == IMS_MODEL_IC && ((rc = dev_alloc(&g->d_lvl, 2ull * g->cap)) || (rc = dev_alloc(&g->d_lvl_dir, g->cap))))
+        return bail(rc);
     if ((rc = dev_alloc(&g->d_status, 4))) return bail(rc);
     *out = g;
     return IMS_OK;
@@ -458,6 +501,30 @@ uint32_t resident_blocks(K kernel, uint32_t cus)
         per_cu = 1;
     }
     return (uint32_t)per_cu * cus;
+}
+
+// IC pull side and direction rule of a run (P.W set): Beamer's switch points
+// (alpha 14, beta 24, those of his direction-optimising BFS) unless given,
+// with alpha scaled by the graph's mean arc probability: a pulled node stops
+// early once its pending trials have joined, which an IC arc brings about
+// only with its probability (p = 1 gives Beamer's BFS rule; measured on the
+// paper's stand-in graphs, the scaled rule keeps low-probability cascades on
+// hub graphs on the push side, where pulling was up to 2.8x slower, and still
+// pulls the high-probability ones, 2-4.7x faster than push alone).
+int set_ic_direction(imsim::SimParams& P, const ims_graph* g, double alpha, double beta, int dir)
+{
+    if (dir < 0 || dir > 2) return fail(IMS_E_INVALID_ARG, "IC direction %d not in 0..2", dir);
+    if (!(alpha >= 0.0) || !(beta >= 0.0)) return fail(IMS_E_INVALID_ARG, "IC switch points must be >= 0 (0 = default)");
+    P.ic_in = g->d_ic_in;
+    P.ic_in_thr = g->d_ic_in_thr;
+    P.lvl_farcs = (unsigned long long*)g->d_lvl;
+    P.lvl_full = g->d_lvl ? (unsigned long long*)g->d_lvl + g->cap : nullptr;
+    P.lvl_dir = g->d_lvl_dir;
+    P.in_total = (uint64_t)P.W * (uint64_t)g->ic_in_m;
+    P.ic_alpha = (float)((alpha > 0.0 ? alpha : 14.0) * g->ic_pbar);
+    P.ic_beta = beta > 0.0 ? (float)beta : 24.0f;
+    P.ic_dir = dir;
+    return IMS_OK;
 }
 
 // One simulation; with level_counts the word-local shape also counts the
@@ -680,6 +747,8 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
     P.slot_steps = nullptr;
     P.status = g->d_status;
     P.cap = g->cap;
+    if ((rc = set_ic_direction(P, g, opts ? opts->ic_alpha : 0.0, opts ? opts->ic_beta : 0.0, opts ? opts->ic_direction : 0)))
+        return rc;
 
     const bool prof = opts && opts->profile && g->prof_count < ims_graph::kProf;
     const uint32_t slot = g->prof_count;
@@ -739,6 +808,10 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
         const uint32_t tau = opts && opts->alpha > 0.0 ? (uint32_t)std::min<double>(opts->alpha * (double)cells, 4e9)
                                                        : (uint32_t)std::min<uint64_t>(cells / 64 + 1, 0xFFFFFFFFull);
         if (g->model == IMS_MODEL_IC) {
+            // per-level direction counters: entries 0 and 1 start at zero,
+            // each level clears the entry two ahead of it
+            if ((rc = fill_async<uint64_t>(g->d_lvl, 2, 0ull, s))) return rc;
+            if ((rc = fill_async<uint64_t>(g->d_lvl + g->cap, 2, 0ull, s))) return rc;
             hipLaunchKernelGGL(imsim::grid_seed_kernel, dim3(std::max<uint32_t>(1, std::min<uint32_t>(blocks, (P.n_seeds * W + 255) / 256))),
                                dim3(imsim::kBlock), 0, s, P, g->model);
             IMS_HIP(hipGetLastError());
@@ -966,6 +1039,8 @@ int simulate_sets_impl(ims_graph* g, const uint64_t* base, const uint32_t* set_o
     P.in_src32 = g->d_in_src32;
     P.node_w = g->d_node_w;
     P.lt_uniform = g->lt_uniform ? 1 : 0;
+    if ((rc = set_ic_direction(P, g, opts ? opts->ic_alpha : 0.0, opts ? opts->ic_beta : 0.0, opts ? opts->ic_direction : 0)))
+        return rc;
     P.A = (uint64_t*)g->sA.p;
     P.N[0] = (uint64_t*)g->sN.p;
     for (int i = 0; i < 3; ++i) P.Q[i] = (uint64_t*)g->sQ[i].p;
@@ -1014,13 +1089,13 @@ struct ims_batch {
     std::vector<imsim::BatchItem> host_items;
     std::vector<uint32_t*> dev_seeds;
     std::vector<double> cost;
-    ims_tuning tuning{2, 0, 8};
+    ims_tuning tuning{2, 0, 8, 0.0, 0.0};
     int device = 0, cus = 0;
     uint64_t max_n = 1;
     uint32_t n_tasks = 0;
     imsim::BatchItem* d_items = nullptr;
     uint64_t* d_tasks = nullptr;
-    uint32_t* d_ctl = nullptr;  // [0] task counter, [1..2] status
+    uint32_t* d_ctl = nullptr;  // [0] task counter, [1..4] status words (steps, guard, -, refused hand-overs)
     ims_graph::Buf sA, sN, sQ0, sQ1, sQ2, sact, sstamp, ssteps;
     uint32_t slots = 0;
     hipGraph_t graph = nullptr;
@@ -1085,6 +1160,13 @@ int batch_plan(ims_batch* b)
                     tasks.push_back(((uint64_t)i << 32) | ((uint64_t)s << 24) | ((uint64_t)part << 16) | w);
     }
     if (tasks.size() >= 0xFFFFFFFFull) return fail(IMS_E_UNSUPPORTED, "ims_batch: more than 2^32 - 2 tasks");
+    // the tuning's IC switch points go into every item
+    for (uint32_t i = 0; i < n_items; ++i) {
+        int rc = set_ic_direction(b->host_items[i].P, b->items[i].graph, b->tuning.ic_alpha, b->tuning.ic_beta, 0);
+        if (rc) return rc;
+    }
+    if (n_items > 0)
+        IMS_HIP(hipMemcpy(b->d_items, b->host_items.data(), n_items * sizeof(imsim::BatchItem), hipMemcpyHostToDevice));
     b->n_tasks = (uint32_t)tasks.size();
     dev_free(b->d_tasks);
     int rc = dev_alloc(&b->d_tasks, tasks.size());
@@ -1115,7 +1197,7 @@ int batch_enqueue(ims_batch* b, hipStream_t s)
         }
         if ((rc = fill_async<unsigned long long>((unsigned long long*)it.total, 1, 0ull, s))) return rc;
     }
-    if ((rc = fill_async<uint32_t>(b->d_ctl, 4, 0u, s))) return rc;
+    if ((rc = fill_async<uint32_t>(b->d_ctl, 8, 0u, s))) return rc;
     imsim::SlotBufs S{b->max_n,
                       (uint64_t*)b->sA.p,
                       (uint64_t*)b->sN.p,
@@ -1183,6 +1265,7 @@ int ims_batch_create(const ims_batch_item* items, uint32_t n_items, const ims_tu
         P.in_src32 = g->d_in_src32;
         P.node_w = g->d_node_w;
         P.lt_uniform = g->lt_uniform ? 1 : 0;
+        if ((rc = set_ic_direction(P, g, b->tuning.ic_alpha, b->tuning.ic_beta, 0))) return bail(rc);
         P.seeds = d;
         P.n_seeds = (uint32_t)sv.size();
         P.cap = g->cap;
@@ -1200,7 +1283,7 @@ int ims_batch_create(const ims_batch_item* items, uint32_t n_items, const ims_tu
     if (!b->host_items.empty() &&
         hipMemcpy(b->d_items, b->host_items.data(), b->host_items.size() * sizeof(imsim::BatchItem), hipMemcpyHostToDevice) != hipSuccess)
         return bail(fail(IMS_E_HIP, "item upload failed"));
-    if ((rc = dev_alloc(&b->d_ctl, 4))) return bail(rc);
+    if ((rc = dev_alloc(&b->d_ctl, 8))) return bail(rc);
     if ((rc = batch_plan(b))) return bail(rc);
     *out = b;
     return IMS_OK;
@@ -1235,35 +1318,68 @@ int ims_batch_autotune(ims_batch* b, int repeats, void* stream, ims_tuning* chos
 {
     if (!b || repeats < 1) return fail(IMS_E_INVALID_ARG, "ims_batch_autotune: bad arguments");
     hipStream_t s = (hipStream_t)stream;
-    const ims_tuning cands[] = {{2, 0, 1}, {2, 0, 4}, {2, 0, 8}, {4, 0, 8}, {2, 1, 8}, {2, 0, 16}, {2, 0, 64}};
     hipEvent_t e0, e1;
     IMS_HIP(hipEventCreate(&e0));
     IMS_HIP(hipEventCreate(&e1));
     double best_ms = 1e300;
     ims_tuning best = b->tuning;
-    std::vector<uint64_t> ref, cur(b->items.size());
+    // every output of every item, read back after each candidate
+    std::vector<uint8_t> ref, cur;
+    auto read_outputs = [&](std::vector<uint8_t>& out) -> int {
+        out.clear();
+        for (const auto& it : b->items) {
+            int64_t n = 0;
+            ims_graph_info(it.graph, &n, nullptr, nullptr);
+            const size_t at = out.size();
+            const size_t tc = (size_t)it.n_trials * 4, nc = it.node_counts ? (size_t)n * 4 : 0;
+            out.resize(at + 8 + tc + nc);
+            IMS_HIP(hipMemcpy(out.data() + at, it.total, 8, hipMemcpyDeviceToHost));
+            IMS_HIP(hipMemcpy(out.data() + at + 8, it.trial_counts, tc, hipMemcpyDeviceToHost));
+            if (nc) IMS_HIP(hipMemcpy(out.data() + at + 8 + tc, it.node_counts, nc, hipMemcpyDeviceToHost));
+        }
+        return IMS_OK;
+    };
     int rc = IMS_OK;
-    for (const ims_tuning& c : cands) {
+    auto trial = [&](const ims_tuning& c) -> int {
         b->tuning = c;
-        if ((rc = batch_plan(b))) break;
-        if ((rc = batch_enqueue(b, s))) break;  // warm-up
+        int r;
+        if ((r = batch_plan(b))) return r;
+        if ((r = batch_enqueue(b, s))) return r;  // warm-up
         IMS_HIP(hipEventRecord(e0, s));
-        for (int r = 0; r < repeats && !rc; ++r) rc = batch_enqueue(b, s);
-        if (rc) break;
+        for (int k = 0; k < repeats; ++k)
+            if ((r = batch_enqueue(b, s))) return r;
         IMS_HIP(hipEventRecord(e1, s));
         IMS_HIP(hipEventSynchronize(e1));
         float ms = 0.f;
         IMS_HIP(hipEventElapsedTime(&ms, e0, e1));
-        for (size_t i = 0; i < b->items.size(); ++i)
-            IMS_HIP(hipMemcpy(&cur[i], b->items[i].total, sizeof(uint64_t), hipMemcpyDeviceToHost));
-        if (ref.empty()) ref = cur;
-        else if (cur != ref) {
-            rc = fail(IMS_E_HIP, "ims_batch_autotune: schedule {%d,%d,%d} changed the results", c.blocks_per_cu, c.order, c.split);
-            break;
-        }
+        if ((r = read_outputs(ref.empty() ? ref : cur))) return r;
+        if (!cur.empty() && cur != ref)
+            return fail(IMS_E_HIP, "ims_batch_autotune: schedule {%d,%d,%d,%g,%g} changed the results", c.blocks_per_cu, c.order,
+                        c.split, c.ic_alpha, c.ic_beta);
         if (ms / repeats < best_ms) {
             best_ms = ms / repeats;
             best = c;
+        }
+        return IMS_OK;
+    };
+    // stage 1: launch shape and task size at the default switch points
+    const ims_tuning shapes[] = {{2, 0, 1, 0, 0}, {2, 0, 4, 0, 0}, {2, 0, 8, 0, 0}, {4, 0, 8, 0, 0},
+                                 {2, 1, 8, 0, 0}, {2, 0, 16, 0, 0}, {2, 0, 64, 0, 0}};
+    for (const ims_tuning& c : shapes)
+        if ((rc = trial(c))) break;
+    // stage 2: IC switch points for the best shape (1e-9: push only)
+    if (!rc) {
+        const ims_tuning base = best;
+        const double alphas[] = {1e-9, 2.0, 50.0, 400.0};
+        for (double a : alphas) {
+            ims_tuning c = base;
+            c.ic_alpha = a;
+            if ((rc = trial(c))) break;
+        }
+        if (!rc) {
+            ims_tuning c = best;
+            c.ic_beta = 4.0;
+            rc = trial(c);
         }
     }
     (void)hipEventDestroy(e0);
@@ -1290,6 +1406,29 @@ int ims_graph_last_status(ims_graph* g, void* stream, uint32_t out[2])
     IMS_HIP(hipMemcpyAsync(out, g->d_status, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, (hipStream_t)stream));
     IMS_HIP(hipStreamSynchronize((hipStream_t)stream));
     if (out[1]) g->zero_dirty = true;
+    return IMS_OK;
+}
+
+int ims_graph_last_counters(ims_graph* g, void* stream, uint32_t out[4])
+{
+    if (!g || !out) return fail(IMS_E_INVALID_ARG, "ims_graph_last_counters: bad arguments");
+    IMS_HIP(hipMemcpyAsync(out, g->d_status, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, (hipStream_t)stream));
+    IMS_HIP(hipStreamSynchronize((hipStream_t)stream));
+    if (out[1]) g->zero_dirty = true;
+    return IMS_OK;
+}
+
+int ims_graph_level_directions(ims_graph* g, uint32_t max_levels, uint32_t* dirs, uint32_t* count, void* stream)
+{
+    if (!g || !count || (max_levels > 0 && !dirs)) return fail(IMS_E_INVALID_ARG, "ims_graph_level_directions: bad arguments");
+    *count = 0;
+    if (g->model != IMS_MODEL_IC || g->last_shape != 2) return IMS_OK;
+    const uint32_t k = std::min<uint32_t>(max_levels, std::min<uint32_t>(g->last_steps, g->cap));
+    if (k > 0) {
+        IMS_HIP(hipMemcpyAsync(dirs, g->d_lvl_dir, k * sizeof(uint32_t), hipMemcpyDeviceToHost, (hipStream_t)stream));
+        IMS_HIP(hipStreamSynchronize((hipStream_t)stream));
+    }
+    *count = k;
     return IMS_OK;
 }
 
@@ -1499,6 +1638,7 @@ int ims_simulate_noalloc(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, 
     P.in_src32 = g->d_in_src32;
     P.node_w = g->d_node_w;
     P.lt_uniform = g->lt_uniform ? 1 : 0;
+    if ((rc = set_ic_direction(P, g, 0.0, 0.0, 0))) return rc;
     P.seeds = (const uint32_t*)(base + L.seeds);
     P.n_seeds = 0;
     P.cap = g->cap;

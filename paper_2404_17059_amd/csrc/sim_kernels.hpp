@@ -121,6 +121,21 @@ struct SimParams {
     uint32_t* slot_steps;       // per slot: last LT stamp value used
     uint32_t* status;        // [0] max steps over words, [1] guard fired
     uint32_t cap;            // step guard
+    // IC pull side: in-CSR (offsets in_off) over the arcs whose threshold is
+    // not 0: per in-arc its source | out-CSR arc id << 32, and its threshold
+    const uint64_t* __restrict__ ic_in;
+    const uint32_t* __restrict__ ic_in_thr;
+    // IC grid shape, direction of each level (Beamer's rule on the trial
+    // words together): lvl_farcs[l] = out-arcs of the (node, word) pairs of
+    // level l's frontier, lvl_full[l] = in-arcs of the pairs whose trials are
+    // all active when level l starts, lvl_dir[l] = 1 push / 2 pull
+    unsigned long long* lvl_farcs;
+    unsigned long long* lvl_full;
+    uint32_t* lvl_dir;
+    uint64_t in_total;   // W * in-arcs: the pull volume of a state with nothing active
+    float ic_alpha;      // push -> pull when frontier out-arcs * alpha > in-arcs of unfinished pairs
+    float ic_beta;       // pull -> push when frontier pairs * beta < W * n
+    int ic_dir;          // 0 = by the rule, 1 = push only, 2 = pull only
 };
 
 // Trials of word w that exist (T trials in all); words past the last one
@@ -495,12 +510,22 @@ __device__ __forceinline__ uint64_t pack_item(uint32_t v, uint32_t w, uint32_t c
     return (uint64_t)v | ((uint64_t)w << 32) | ((uint64_t)chunk << 44);
 }
 
-__device__ __forceinline__ void grid_ic_enqueue(const SimParams& P, uint64_t* Q, uint32_t* count, uint32_t v, uint32_t w)
+// Queue the chunks of frontier pair (v, w) for the next level, and add its
+// out-arcs to that level's frontier volume.
+__device__ __forceinline__ void grid_ic_enqueue(const SimParams& P, uint64_t* Q, uint32_t* count, uint32_t v, uint32_t w,
+                                                unsigned long long* farcs)
 {
     const uint64_t deg = (uint64_t)(P.off[v + 1] - P.off[v]);
     const uint32_t nc = (uint32_t)((deg + kChunk - 1) / kChunk);
     const uint32_t pos = atomicAdd(count, nc);
     for (uint32_t c = 0; c < nc; ++c) Q[pos + c] = pack_item(v, w, c);
+    atomicAdd(farcs, (unsigned long long)deg);
+}
+
+// In-arcs of v on the pull side (IC in-CSR).
+__device__ __forceinline__ unsigned long long ic_in_deg(const SimParams& P, uint32_t v)
+{
+    return (unsigned long long)(P.in_off[v + 1] - P.in_off[v]);
 }
 
 // Seeds are active in every trial; for IC, seeds with out-arcs form level 0.
@@ -513,14 +538,160 @@ __global__ __launch_bounds__(kBlock) void grid_seed_kernel(SimParams P, int mode
         const uint32_t w = (uint32_t)(i % P.W);
         const uint64_t vm = valid_mask(w, P.W, P.T);
         P.A[(uint64_t)w * n + s] = vm;
-        if (model == 0 && P.off[s + 1] > P.off[s]) {
-            P.N[0][(uint64_t)w * n + s] = vm;
-            grid_ic_enqueue(P, P.Q[0], &P.qcount[0], s, w);
+        if (model == 0) {
+            if (vm) atomicAdd(&P.lvl_full[0], ic_in_deg(P, s));
+            if (P.off[s + 1] > P.off[s]) {
+                P.N[0][(uint64_t)w * n + s] = vm;
+                grid_ic_enqueue(P, P.Q[0], &P.qcount[0], s, w, &P.lvl_farcs[0]);
+            }
         }
     }
 }
 
-// IC level `lev`: clear level lev-1's masks, then expand level lev's queue.
+// Direction of IC level `lev` (every workgroup reaches the same answer from
+// the same counters, which the previous level completed).  Beamer's rule with
+// (node, word) pairs in place of nodes: leave push when the frontier's
+// out-arcs exceed 1 / alpha of the in-arcs still to be pulled (those of pairs
+// with an inactive trial), go back to push when the frontier holds fewer than
+// 1 / beta of all pairs.
+__device__ __forceinline__ bool grid_ic_pull(const SimParams& P, uint32_t lev, uint32_t cnt)
+{
+    if (P.ic_dir == 1) return false;
+    if (P.ic_dir == 2) return true;
+    const bool was_pull = lev > 0 && load_relaxed32(&P.lvl_dir[lev - 1]) == 2u;
+    if (was_pull) return (double)cnt * (double)P.ic_beta >= (double)P.W * (double)P.n;
+    const unsigned long long full = __hip_atomic_load(&P.lvl_full[lev], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long farcs = __hip_atomic_load(&P.lvl_farcs[lev], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const double todo = P.in_total > full ? (double)(P.in_total - full) : 0.0;
+    return (double)farcs * (double)P.ic_alpha > todo;
+}
+
+// In-arcs above which a pulled pair is walked by its whole wavefront.
+constexpr uint32_t kPullLaneDeg = 32;
+
+// Pull walk of pair (v, w) by the calling lane alone: eight in-arcs per round,
+// their loads issued together.  Returns the trials that joined; `pend` keeps
+// the ones still pending.
+__device__ __forceinline__ uint64_t ic_pull_lane(const SimParams& P, const uint64_t* __restrict__ Fw, int64_t k0, int64_t k1,
+                                                 uint32_t w, uint64_t& pend)
+{
+    uint64_t got = 0;
+    for (int64_t k = k0; k < k1 && pend; k += 8) {
+        uint64_t sa[8], f[8];
+        uint32_t th[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            sa[j] = k + j < k1 ? P.ic_in[k + j] : 0ull;
+            th[j] = k + j < k1 ? P.ic_in_thr[k + j] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) f[j] = k + j < k1 ? Fw[(uint32_t)sa[j]] : 0ull;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const uint64_t todo = f[j] & pend;
+            if (todo == 0) continue;
+            const uint64_t live = ic_live(todo, th[j], sa[j] >> 32, w, P.seed);
+            got |= live;
+            pend &= ~live;
+        }
+    }
+    return got;
+}
+
+// Pull walk of one pair by the whole wavefront (every lane calls it with the
+// same arguments): 64 in-arcs per round, lane-strided, the joined trials
+// OR-ed over the wavefront after each round so that the walk stops as soon as
+// no trial is pending.
+__device__ __forceinline__ uint64_t ic_pull_wave(const SimParams& P, const uint64_t* __restrict__ Fw, int64_t k0, int64_t k1,
+                                                 uint32_t w, uint64_t& pend, uint32_t lane)
+{
+    uint64_t got = 0;
+    for (int64_t k = k0; k < k1 && pend; k += 64) {
+        uint64_t mine = 0;
+        if (k + lane < k1) {
+            const uint64_t sa = P.ic_in[k + lane];
+            const uint64_t todo = Fw[(uint32_t)sa] & pend;
+            if (todo) mine = ic_live(todo, P.ic_in_thr[k + lane], sa >> 32, w, P.seed);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) mine |= __shfl_xor(mine, o);
+        mine = uniform64(mine);
+        got |= mine;
+        pend &= ~mine;
+    }
+    return got;
+}
+
+// IC level `lev` by pulling: every (node v, word w) pair with an inactive
+// trial walks v's in-arcs (u, e) and takes, for the pending trials in which u
+// is in level lev's frontier, arc e's coin; it stops once every pending trial
+// has joined.  A pair is written by its own lane only (pairs with more than
+// kPullLaneDeg in-arcs are walked by the wavefront, then written by their
+// lane).  New pairs join the next level's queue exactly as a push would put
+// them there.
+__device__ __forceinline__ void grid_ic_pull_level(const SimParams& P, uint32_t lev)
+{
+    const uint64_t n = (uint64_t)P.n;
+    const uint64_t pairs = (uint64_t)P.W * n;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t wave0 = (uint64_t)blockIdx.x * kBlock + (threadIdx.x & ~63u);
+    const uint64_t nthreads = (uint64_t)gridDim.x * kBlock;
+    if (wave0 >= pairs) return;
+    const uint64_t* F = P.N[lev % 3];
+    uint64_t* Nn = P.N[(lev + 1) % 3];
+    uint64_t* Qn = P.Q[(lev + 1) % 3];
+    uint32_t* qnext = &P.qcount[lev + 1];
+    // (w, v) of pair i = w * n + v, advanced by nthreads without a division;
+    // the loop runs the same rounds on every lane of a wavefront
+    const uint64_t i0 = wave0 + lane;
+    uint64_t w = i0 / n, v = i0 - w * n;
+    const uint64_t dw = nthreads / n, dv = nthreads - dw * n;
+    for (uint64_t base = wave0; base < pairs; base += nthreads) {
+        const bool have = w < P.W;
+        const uint64_t at = w * n + v;
+        const uint64_t vm = have ? valid_mask((uint32_t)w, P.W, P.T) : 0ull;
+        const uint64_t a = have ? P.A[at] : 0ull;
+        uint64_t pend = vm & ~a;
+        int64_t k0 = 0, k1 = 0;
+        if (pend) {
+            k0 = P.in_off[v];
+            k1 = P.in_off[v + 1];
+        }
+        const uint64_t* Fw = F + w * n;
+        uint64_t got = 0;
+        const bool big = pend != 0 && (uint64_t)(k1 - k0) > kPullLaneDeg;
+        if (pend && !big) got = ic_pull_lane(P, Fw, k0, k1, (uint32_t)w, pend);
+        uint64_t bigs = __ballot(big);
+        while (bigs) {
+            const int j = __builtin_ctzll(bigs);
+            bigs &= bigs - 1;
+            uint64_t pj = uniform64(__shfl(pend, j));
+            const uint64_t g = ic_pull_wave(P, F + uniform64(__shfl(w, j)) * n, (int64_t)uniform64((uint64_t)__shfl(k0, j)),
+                                            (int64_t)uniform64((uint64_t)__shfl(k1, j)), (uint32_t)uniform64(__shfl(w, j)), pj, lane);
+            if (lane == (uint32_t)j) {
+                got = g;
+                pend = pj;
+            }
+        }
+        if (got) {
+            P.A[at] = a | got;
+            if (pend == 0) atomicAdd(&P.lvl_full[lev + 1], ic_in_deg(P, (uint32_t)v));
+            if (P.off[v + 1] > P.off[v]) {
+                Nn[at] = got;
+                grid_ic_enqueue(P, Qn, qnext, (uint32_t)v, (uint32_t)w, &P.lvl_farcs[lev + 1]);
+            }
+        }
+        v += dv;
+        w += dw;
+        if (v >= n) {
+            v -= n;
+            ++w;
+        }
+    }
+}
+
+// IC level `lev`: clear level lev-1's masks, then expand level lev's queue
+// by push or pull (grid_ic_pull).
 // Masks and queues rotate over three buffers: level l reads buffer l%3, writes
 // (l+1)%3 and clears (l+2)%3, which held level l-1's frontier.
 __global__ __launch_bounds__(kBlock) void grid_ic_level_kernel(SimParams P, uint32_t lev)
@@ -543,11 +714,27 @@ __global__ __launch_bounds__(kBlock) void grid_ic_level_kernel(SimParams P, uint
         if (gtid == 0) P.status[1] = 1;
         return;
     }
+    const bool pull = grid_ic_pull(P, lev, cnt);
+    if (gtid == 0) {
+        P.lvl_dir[lev] = pull ? 2u : 1u;
+        atomicAdd(&P.lvl_full[lev + 1], __hip_atomic_load(&P.lvl_full[lev], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        // level lev + 1 adds into entry lev + 2 (the host clears entries 0, 1)
+        if (lev + 2 < P.cap) {
+            P.lvl_farcs[lev + 2] = 0;
+            P.lvl_full[lev + 2] = 0;
+        }
+    }
+    if (pull) {
+        grid_ic_pull_level(P, lev);
+        return;
+    }
     const uint64_t* Qc = P.Q[lev % 3];
     const uint64_t* Nc = P.N[lev % 3];
     uint64_t* Nn = P.N[(lev + 1) % 3];
     uint64_t* Qn = P.Q[(lev + 1) % 3];
     uint32_t* qnext = &P.qcount[lev + 1];
+    unsigned long long* farcs = &P.lvl_farcs[lev + 1];
+    unsigned long long* full = &P.lvl_full[lev + 1];
     const uint32_t lane = threadIdx.x & 63u;
     for (uint64_t itx = gtid >> 6; itx < cnt; itx += nthreads >> 6) {
         const uint64_t item = Qc[itx];
@@ -555,6 +742,7 @@ __global__ __launch_bounds__(kBlock) void grid_ic_level_kernel(SimParams P, uint
         const uint32_t w = (uint32_t)(item >> 32) & 0xFFFu;
         const uint32_t chunk = (uint32_t)(item >> 44);
         const uint64_t mask = load_relaxed(&Nc[(uint64_t)w * n + u]);
+        const uint64_t vm = valid_mask(w, P.W, P.T);
         const int64_t row_end = P.off[u + 1];
         const int64_t e0 = P.off[u] + (int64_t)chunk * kChunk;
         const int64_t e1 = e0 + (int64_t)kChunk < row_end ? e0 + (int64_t)kChunk : row_end;
@@ -567,9 +755,12 @@ __global__ __launch_bounds__(kBlock) void grid_ic_level_kernel(SimParams P, uint
             if (todo == 0) continue;
             const uint64_t live = ic_live(todo, th, (uint64_t)e, w, P.seed);
             if (live == 0) continue;
-            const uint64_t fresh = live & ~atomic_or64(&Aw[v], live);
-            if (fresh == 0 || P.off[v + 1] == P.off[v]) continue;
-            if (atomic_or64(&Nn[(uint64_t)w * n + v], fresh) == 0) grid_ic_enqueue(P, Qn, qnext, v, w);
+            const uint64_t old = atomic_or64(&Aw[v], live);
+            const uint64_t fresh = live & ~old;
+            if (fresh == 0) continue;
+            if (((old | live) & vm) == vm) atomicAdd(full, ic_in_deg(P, v));  // the pair's last trials joined
+            if (P.off[v + 1] == P.off[v]) continue;
+            if (atomic_or64(&Nn[(uint64_t)w * n + v], fresh) == 0) grid_ic_enqueue(P, Qn, qnext, v, w, farcs);
         }
     }
 }
@@ -1365,8 +1556,12 @@ constexpr uint32_t kBigMax = 64;   // such nodes handed over per step (more are 
 
 struct TaskShared {
     uint32_t cnt[2];
+    uint32_t farcs[2];  // IC: out-arcs of the frontier lists cnt[] count
+    uint32_t full;      // IC: in-arcs of nodes whose trials of the task are all active
+    uint32_t pull;      // IC: the current step pulls
     uint32_t next_item;
     uint32_t nbig;
+    uint32_t nover;         // hand-overs refused because kBigMax nodes were already handed over
     uint32_t big[kBigMax];  // frontier-list positions of the nodes the workgroup walks together
     uint32_t cand;
     uint32_t act;
@@ -1430,9 +1625,76 @@ __device__ __forceinline__ bool hand_over(uint32_t it, uint32_t lane, TaskShared
     uint32_t pos = 0;
     if (lane == 0) pos = atomicAdd(&sh.nbig, 1u);
     pos = uniform32(__shfl(pos, 0));
-    if (pos >= kBigMax) return false;
+    if (pos >= kBigMax) {
+        if (lane == 0) atomicAdd(&sh.nover, 1u);  // counted for the run's status word 3
+        return false;
+    }
     if (lane == 0) sh.big[pos] = it;
     return true;
+}
+
+// One IC step of a task by pulling: the frontier masks are scattered into the
+// dense row Nw (zero between steps); then every node v with a pending trial
+// of the task walks its in-arcs (u, e) and takes arc e's coin (keyed by its
+// out-CSR id, as a push draws it) for the pending trials in which u is in the
+// frontier, until every pending trial has joined.  A node is owned by one
+// lane, or by one wavefront when it has more than kPullLaneDeg in-arcs.  New nodes
+// go to the next list with their masks; the caller clears Nw afterwards.
+__device__ __forceinline__ void ic_task_pull_step(const SimParams& P, const TaskCtx& c, TaskShared& sh, uint32_t cur, uint32_t cnt,
+                                                  uint64_t vm, bool levels)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t w = c.w;
+    const uint32_t nxt = cur ^ 1u;
+    const uint32_t* Lc = cur ? c.L[1] : c.L[0];
+    const uint64_t* Mc = cur ? c.M[1] : c.M[0];
+    for (uint32_t i = threadIdx.x; i < cnt; i += kTaskBlock) c.Nw[Lc[i]] = Mc[i];
+    __syncthreads();
+    const uint64_t* F = c.Nw;
+    // node v (owned by the calling lane) gained trials `got`
+    auto join = [&](uint32_t v, uint64_t a, uint64_t got, bool now_full) {
+        c.Aw[v] = a | got;
+        if (levels) count_level_bits(sh, got);
+        if (c.act && a == 0) c.act[atomicAdd(&sh.act, 1u)] = v;
+        if (now_full) atomicAdd(&sh.full, (uint32_t)ic_in_deg(P, v));
+        const int64_t o0 = P.off[v], o1 = P.off[v + 1];
+        if (o1 > o0) {
+            const uint32_t pos = atomicAdd(&sh.cnt[nxt], 1u);
+            (nxt ? c.L[1] : c.L[0])[pos] = v;
+            (nxt ? c.M[1] : c.M[0])[pos] = got;
+            atomicAdd(&sh.farcs[nxt], (uint32_t)(o1 - o0));
+        }
+    };
+    const uint64_t n = (uint64_t)P.n;
+    for (uint64_t base = threadIdx.x & ~63u; base < n; base += kTaskBlock) {
+        const uint64_t v = base + lane;
+        uint64_t a = 0, pend = 0;
+        int64_t k0 = 0, k1 = 0;
+        if (v < n) {
+            a = c.Aw[v];
+            pend = vm & ~(a | (c.Bw ? c.Bw[v] : 0ull));
+            if (pend) {
+                k0 = P.in_off[v];
+                k1 = P.in_off[v + 1];
+            }
+        }
+        const bool big = pend != 0 && (uint64_t)(k1 - k0) > kPullLaneDeg;
+        if (pend && !big) {
+            uint64_t rest = pend;
+            const uint64_t got = ic_pull_lane(P, F, k0, k1, w, rest);
+            if (got) join((uint32_t)v, a, got, rest == 0);
+        }
+        // nodes with many in-arcs: the wavefront walks them 64 arcs at a time
+        uint64_t bigs = __ballot(big);
+        while (bigs) {
+            const int j = __builtin_ctzll(bigs);
+            bigs &= bigs - 1;
+            uint64_t rest = uniform64(__shfl(pend, j));
+            const uint64_t got = ic_pull_wave(P, F, (int64_t)uniform64((uint64_t)__shfl(k0, j)),
+                                              (int64_t)uniform64((uint64_t)__shfl(k1, j)), w, rest, lane);
+            if (got && lane == (uint32_t)j) join((uint32_t)v, a, got, rest == 0);
+        }
+    }
 }
 
 // IC cascade of one task.  Per step every wavefront takes frontier entries
@@ -1446,10 +1708,14 @@ __device__ __forceinline__ uint32_t ic_task(const SimParams& P, const TaskCtx& c
     const uint64_t vm = valid_mask(w, P.W, P.T) & c.tmask;
     const bool narrow = c.group < 8;
     const bool levels = P.level_counts != nullptr;
+    const bool can_pull = P.ic_in != nullptr && P.ic_dir != 1;
     if (threadIdx.x == 0) {
         sh.cnt[0] = 0;
         sh.cnt[1] = 0;
         sh.act = 0;
+        sh.farcs[0] = 0;
+        sh.full = 0;
+        sh.pull = 0;
     }
     if (levels && threadIdx.x < 64) sh.lvl[threadIdx.x] = 0;
     __syncthreads();
@@ -1460,10 +1726,13 @@ __device__ __forceinline__ uint32_t ic_task(const SimParams& P, const TaskCtx& c
         c.Aw[sd] = nb;
         if (levels) count_level_bits(sh, nb);
         if (c.act) c.act[atomicAdd(&sh.act, 1u)] = sd;
-        if (P.off[sd + 1] > P.off[sd]) {
+        if (can_pull) atomicAdd(&sh.full, (uint32_t)ic_in_deg(P, sd));
+        const int64_t o0 = P.off[sd], o1 = P.off[sd + 1];
+        if (o1 > o0) {
             const uint32_t pos = atomicAdd(&sh.cnt[0], 1u);
             c.L[0][pos] = sd;
             c.M[0][pos] = nb;
+            atomicAdd(&sh.farcs[0], (uint32_t)(o1 - o0));
         }
     }
     __syncthreads();
@@ -1484,14 +1753,34 @@ __device__ __forceinline__ uint32_t ic_task(const SimParams& P, const TaskCtx& c
         __syncthreads();
         if (threadIdx.x == 0) {
             sh.cnt[nxt] = 0;
+            sh.farcs[nxt] = 0;
             sh.next_item = 0;
             sh.nbig = 0;
+            // direction of this step: Beamer's rule on the task's own
+            // frontier (push -> pull when its out-arcs times alpha exceed the
+            // in-arcs of nodes with a pending trial; pull -> push when it
+            // holds fewer than n / beta nodes)
+            bool pull = false;
+            if (can_pull) {
+                if (P.ic_dir == 2) {
+                    pull = true;
+                } else if (sh.pull) {
+                    pull = (double)cnt * (double)P.ic_beta >= (double)P.n;
+                } else {
+                    const uint64_t in_m = (uint64_t)P.in_off[P.n];
+                    const double todo = in_m > sh.full ? (double)(in_m - sh.full) : 0.0;
+                    pull = (double)sh.farcs[cur] * (double)P.ic_alpha > todo;
+                }
+            }
+            sh.pull = pull ? 1u : 0u;
         }
         __syncthreads();
+        const bool pull = sh.pull != 0;
         // one out-arc e = (u, v) of a frontier node whose new trials are `mask`
         auto exam = [&](int64_t e, uint32_t v, uint32_t th, uint64_t mask) {
             if (th == 0) return;
-            const uint64_t todo = mask & ~(c.Aw[v] | (c.Bw ? c.Bw[v] : 0ull));
+            const uint64_t bw = c.Bw ? c.Bw[v] : 0ull;
+            const uint64_t todo = mask & ~(c.Aw[v] | bw);
             if (todo == 0) return;
             const uint64_t live = ic_live(todo, th, (uint64_t)e, w, P.seed);
             if (live == 0) return;
@@ -1499,13 +1788,19 @@ __device__ __forceinline__ uint32_t ic_task(const SimParams& P, const TaskCtx& c
             const uint64_t fresh = live & ~old;
             if (levels) count_level_bits(sh, fresh);
             if (c.act && old == 0) c.act[atomicAdd(&sh.act, 1u)] = v;
-            if (fresh == 0 || P.off[v + 1] == P.off[v]) return;
+            if (fresh == 0) return;
+            if (can_pull && ((old | live | bw) & vm) == vm) atomicAdd(&sh.full, (uint32_t)ic_in_deg(P, v));
+            const int64_t o0 = P.off[v], o1 = P.off[v + 1];
+            if (o1 == o0) return;
             if (atomic_or64(&c.Nw[v], fresh) == 0) {
                 const uint32_t pos = atomicAdd(&sh.cnt[nxt], 1u);
                 (nxt ? c.L[1] : c.L[0])[pos] = v;
+                atomicAdd(&sh.farcs[nxt], (uint32_t)(o1 - o0));
             }
         };
-        if (narrow) {
+        if (pull) {
+            ic_task_pull_step(P, c, sh, cur, cnt, vm, levels);
+        } else if (narrow) {
             // a lane per frontier node of at most kNarrowDeg out-arcs; the
             // wavefront walks larger ones together
             for (;;) {
@@ -1555,7 +1850,7 @@ __device__ __forceinline__ uint32_t ic_task(const SimParams& P, const TaskCtx& c
         }
         // the handed-over nodes, every wavefront on each
         __syncthreads();
-        {
+        if (!pull) {
             const uint32_t nb = sh.nbig < kBigMax ? sh.nbig : kBigMax;
             for (uint32_t b = 0; b < nb; ++b) {
                 const uint32_t it = sh.big[b];
@@ -1567,11 +1862,17 @@ __device__ __forceinline__ uint32_t ic_task(const SimParams& P, const TaskCtx& c
         }
         __syncthreads();
         if (levels) flush_level(P, sh, w, steps);
-        const uint32_t nc = sh.cnt[nxt];
-        for (uint32_t i = threadIdx.x; i < nc; i += kTaskBlock) {
-            const uint32_t v = (nxt ? c.L[1] : c.L[0])[i];
-            (nxt ? c.M[1] : c.M[0])[i] = load_relaxed(&c.Nw[v]);
-            c.Nw[v] = 0;
+        if (pull) {
+            // the next list carries its masks already; clear the dense
+            // frontier masks the step pulled from
+            for (uint32_t i = threadIdx.x; i < cnt; i += kTaskBlock) c.Nw[(cur ? c.L[1] : c.L[0])[i]] = 0;
+        } else {
+            const uint32_t nc = sh.cnt[nxt];
+            for (uint32_t i = threadIdx.x; i < nc; i += kTaskBlock) {
+                const uint32_t v = (nxt ? c.L[1] : c.L[0])[i];
+                (nxt ? c.M[1] : c.M[0])[i] = load_relaxed(&c.Nw[v]);
+                c.Nw[v] = 0;
+            }
         }
         __syncthreads();
         cur = nxt;
@@ -1884,6 +2185,7 @@ __global__ __launch_bounds__(kTaskBlock, 2) void word_kernel(SimParams P, uint64
     const uint32_t n_tasks = kSets ? P.n_sets * P.W : P.W;
     uint32_t max_steps = 0;
     bool guard = false;
+    if (threadIdx.x == 0) sh.nover = 0;
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) sh.task = atomicAdd(P.task_counter, 1u);
@@ -1944,6 +2246,7 @@ __global__ __launch_bounds__(kTaskBlock, 2) void word_kernel(SimParams P, uint64
     }
     if (threadIdx.x == 0) {
         atomicMax(&P.status[0], max_steps);
+        if (sh.nover) atomicAdd(&P.status[3], sh.nover);
         if (guard) P.status[1] = 1;
     }
 }
@@ -1994,6 +2297,7 @@ __device__ __forceinline__ void slot_tasks(TaskOf task_of, uint32_t n_tasks, uin
     const uint64_t max_n = S.max_n;
     uint32_t max_steps = 0;
     bool guard = false;
+    if (threadIdx.x == 0) sh.nover = 0;
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) sh.task = atomicAdd(task_counter, 1u);
@@ -2032,6 +2336,7 @@ __device__ __forceinline__ void slot_tasks(TaskOf task_of, uint32_t n_tasks, uin
     }
     if (threadIdx.x == 0) {
         atomicMax(&status[0], max_steps);
+        if (sh.nover) atomicAdd(&status[3], sh.nover);
         if (guard) status[1] = 1;
     }
 }
