@@ -20,7 +20,7 @@ namespace imsim_mpnn {
 constexpr int kHidden = 64;    // channels of every hidden layer
 constexpr int kIn = 16;        // padded width of the input features (4 used)
 constexpr int kThreads = 256;  // threads of every workgroup here
-constexpr int kWStage = 128;   // rows per LDS stage of the weight-gradient kernel
+constexpr int kWStage = 128;   // rows_per of the weight-gradient kernel is a multiple of this (4 waves x 32 rows)
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -250,16 +250,26 @@ __global__ void __launch_bounds__(kThreads) dense_fwd_kernel(int64_t R, const ui
     const int64_t tiles = (R + 15) / 16;
     const int64_t wave = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
     const int64_t waves = (int64_t)gridDim.x * (kThreads / 64);
-    for (int64_t t = wave; t < tiles; t += waves) {
+    // the next tile's rows are loaded before the current tile is computed
+    auto load = [&](int64_t t, u32x4 (&Bf)[KS]) {
         const int64_t row = t * 16 + l16;
         const bool ok = row < R;
-        u32x4 Bf[KS];
         #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
             const int kc = 32 * ks + 8 * g;
             const uint16_t* src = kc < D ? Xs + row * D + kc : Xn + row * D + (kc - D);
             Bf[ks] = ok ? *(const u32x4*)src : u32x4{0u, 0u, 0u, 0u};
         }
+    };
+    u32x4 Bn[KS];
+    load(wave, Bn);
+    for (int64_t t = wave; t < tiles; t += waves) {
+        const int64_t row = t * 16 + l16;
+        const bool ok = row < R;
+        u32x4 Bf[KS];
+        #pragma unroll
+        for (int ks = 0; ks < KS; ++ks) Bf[ks] = Bn[ks];
+        load(t + waves, Bn);
         floatx4 acc[4];
         #pragma unroll
         for (int ct = 0; ct < 4; ++ct) {
@@ -307,13 +317,21 @@ __global__ void __launch_bounds__(kThreads) dense_bwd_data_kernel(int64_t R, con
     const int64_t tiles = (R + 15) / 16;
     const int64_t wave = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
     const int64_t waves = (int64_t)gridDim.x * (kThreads / 64);
-    for (int64_t t = wave; t < tiles; t += waves) {
+    // the next tile's rows are loaded before the current tile is computed
+    auto load = [&](int64_t t, u32x4 (&Bf)[2]) {
         const int64_t row = t * 16 + l16;
         const bool ok = row < R;
-        u32x4 Bf[2];
         #pragma unroll
         for (int ks = 0; ks < 2; ++ks)
             Bf[ks] = ok ? *(const u32x4*)(dZ + row * kHidden + 32 * ks + 8 * g) : u32x4{0u, 0u, 0u, 0u};
+    };
+    u32x4 Bn[2];
+    load(wave, Bn);
+    for (int64_t t = wave; t < tiles; t += waves) {
+        const int64_t row = t * 16 + l16;
+        const bool ok = row < R;
+        u32x4 Bf[2] = {Bn[0], Bn[1]};
+        load(t + waves, Bn);
         #pragma unroll
         for (int kt = 0; kt < KT; ++kt) {
             floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -330,12 +348,74 @@ __global__ void __launch_bounds__(kThreads) dense_bwd_data_kernel(int64_t R, con
 }
 
 // ---------------------------------------------------------------------------
+// 8x8 transpose of 16-bit values across each aligned group of 8 lanes: on
+// entry lane 8q + j holds row j of its group's matrix (element i in half
+// (i & 1) of word i >> 1), on exit it holds column j.  Three rounds swap the
+// off-diagonal blocks of side 4, 2, 1 between lanes j and j ^ s; each lane
+// sends the half of its row that its partner needs.
+
+__device__ __forceinline__ u32x4 transpose8_b16(u32x4 v, uint32_t lane)
+{
+    {
+        const bool up = (lane & 4u) != 0;
+        const uint32_t r0 = (uint32_t)__shfl_xor((int)(up ? v[0] : v[2]), 4);
+        const uint32_t r1 = (uint32_t)__shfl_xor((int)(up ? v[1] : v[3]), 4);
+        if (up) {
+            v[0] = r0;
+            v[1] = r1;
+        } else {
+            v[2] = r0;
+            v[3] = r1;
+        }
+    }
+    {
+        const bool up = (lane & 2u) != 0;
+        const uint32_t r0 = (uint32_t)__shfl_xor((int)(up ? v[0] : v[1]), 2);
+        const uint32_t r1 = (uint32_t)__shfl_xor((int)(up ? v[2] : v[3]), 2);
+        if (up) {
+            v[0] = r0;
+            v[2] = r1;
+        } else {
+            v[1] = r0;
+            v[3] = r1;
+        }
+    }
+    {
+        const bool up = (lane & 1u) != 0;
+        // the lower lane sends its odd elements (high halves), the upper lane
+        // its even ones (low halves), two per word
+        const uint32_t p0 = up ? __builtin_amdgcn_perm(v[1], v[0], 0x05040100u) : __builtin_amdgcn_perm(v[1], v[0], 0x07060302u);
+        const uint32_t p1 = up ? __builtin_amdgcn_perm(v[3], v[2], 0x05040100u) : __builtin_amdgcn_perm(v[3], v[2], 0x07060302u);
+        const uint32_t q0 = (uint32_t)__shfl_xor((int)p0, 1);
+        const uint32_t q1 = (uint32_t)__shfl_xor((int)p1, 1);
+        if (up) {
+            v[0] = __builtin_amdgcn_perm(v[0], q0, 0x07060100u);
+            v[1] = __builtin_amdgcn_perm(v[1], q0, 0x07060302u);
+            v[2] = __builtin_amdgcn_perm(v[2], q1, 0x07060100u);
+            v[3] = __builtin_amdgcn_perm(v[3], q1, 0x07060302u);
+        } else {
+            v[0] = __builtin_amdgcn_perm(q0, v[0], 0x05040100u);
+            v[1] = __builtin_amdgcn_perm(q0, v[1], 0x07060100u);
+            v[2] = __builtin_amdgcn_perm(q1, v[2], 0x05040100u);
+            v[3] = __builtin_amdgcn_perm(q1, v[3], 0x07060100u);
+        }
+    }
+    return v;
+}
+
+// ---------------------------------------------------------------------------
 // Dense layer, weight and bias gradients.  dW = [Xs | Xn]^T dZ ([2D][64]) and
 // db = column sums of dZ, over rows [0, R).  Workgroup `blk` takes rows
-// [blk*rows_per, (blk+1)*rows_per) (rows_per a multiple of kWStage), stages
-// kWStage rows of dZ and X transposed into LDS, and accumulates dW^T tiles
-// (channel x k) with MFMA over the row axis.  Partials: part[blk * stride]
-// holds dW ([2D][64]) followed by db ([64]).
+// [blk*rows_per, (blk+1)*rows_per) (rows_per a multiple of 128); its four
+// wavefronts take 32-row blocks in turn.  MFMA reduces over the row axis:
+// dW^T tile (channel x column) += dZ^T (channel x 32 rows) X (32 rows x
+// column).  A lane loads 16 bytes of one row (lane L: row 8 (L >> 4) +
+// (L & 7) of the block, channels 8 ((L >> 3) & 1) .. + 7 of a 16-wide tile)
+// and an 8x8 transpose across its group of 8 lanes turns that into the
+// operand layout (eight consecutive rows of channel L & 15), so no staging in
+// LDS is needed.  The wavefronts' tiles are added in LDS in wavefront order,
+// then written as the workgroup's partial: part[blk * stride] holds dW
+// ([2D][64]) followed by db ([64]).
 
 template <int D>
 __global__ void __launch_bounds__(kThreads) dense_bwd_weight_kernel(int64_t R, int64_t rows_per,
@@ -345,84 +425,85 @@ __global__ void __launch_bounds__(kThreads) dense_bwd_weight_kernel(int64_t R, i
                                                                     float* __restrict__ part, int64_t stride)
 {
     constexpr int K = 2 * D;
-    constexpr int P = kWStage + 8;           // LDS pitch (bf16) of transposed rows
-    constexpr int NT = 4 * (K / 16);         // output tiles (channel tile x k tile)
-    constexpr int TPW = NT / 4;              // tiles per wave
-    __shared__ uint16_t dZt[kHidden * P];
-    __shared__ uint16_t Xt[K * P];
-    __shared__ float red[kThreads / 8][kHidden + 1];
+    constexpr int KT = K / 16;      // 16-wide column tiles of [Xs | Xn]
+    constexpr int CT = kHidden / 16;  // 16-wide channel tiles of dZ
+    constexpr int kWaves = kThreads / 64;
+    __shared__ floatx4 red[CT * KT][64];
+    __shared__ float redb[CT][16];
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wv = tid >> 6;
+    const uint32_t lane = tid & 63;
+    const int wv = tid >> 6;
     const int l16 = lane & 15, g = lane >> 4;
     const int64_t r_begin = (int64_t)blockIdx.x * rows_per;
     const int64_t r_end = r_begin + rows_per < R ? r_begin + rows_per : R;
+    const int rl = 8 * (int)(lane >> 4) + (int)(lane & 7);  // the row of a block this lane loads
+    const int half = (int)((lane >> 3) & 1u);               // which 8 columns of a 16-wide tile
 
-    floatx4 acc[TPW];
+    floatx4 acc[CT][KT];
     #pragma unroll
-    for (int i = 0; i < TPW; ++i) acc[i] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-    float db[8];
-    #pragma unroll
-    for (int i = 0; i < 8; ++i) db[i] = 0.0f;
-
-    for (int64_t r0 = r_begin; r0 < r_end; r0 += kWStage) {
-        // stage dZ: kWStage rows x 8 chunks of 8 channels
+    for (int ct = 0; ct < CT; ++ct)
         #pragma unroll
-        for (int p = 0; p < kWStage * 8 / kThreads; ++p) {
-            const int ci = tid + kThreads * p;
-            const int row = ci >> 3, ch = ci & 7;
-            const int64_t r = r0 + row;
-            u32x4 raw = r < r_end ? *(const u32x4*)(dZ + r * kHidden + 8 * ch) : u32x4{0u, 0u, 0u, 0u};
+        for (int kt = 0; kt < KT; ++kt) acc[ct][kt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    float db[CT];
+    #pragma unroll
+    for (int ct = 0; ct < CT; ++ct) db[ct] = 0.0f;
+
+    for (int64_t r0 = r_begin + 32 * wv; r0 < r_end; r0 += 32 * kWaves) {
+        const int64_t r = r0 + rl;
+        const bool ok = r < r_end;
+        u32x4 a[CT], b[KT];
+        #pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+            a[ct] = ok ? *(const u32x4*)(dZ + r * kHidden + 16 * ct + 8 * half) : u32x4{0u, 0u, 0u, 0u};
+        #pragma unroll
+        for (int kt = 0; kt < KT; ++kt) {
+            const int c = 16 * kt + 8 * half;
+            const uint16_t* src = c < D ? Xs + r * D + c : Xn + r * D + (c - D);
+            b[kt] = ok ? *(const u32x4*)src : u32x4{0u, 0u, 0u, 0u};
+        }
+        #pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+            a[ct] = transpose8_b16(a[ct], lane);
             float f[8];
-            unpack8(raw, f);
+            unpack8(a[ct], f);
             #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                db[q] += f[q];
-                dZt[(8 * ch + q) * P + row] = (uint16_t)(q & 1 ? raw[q >> 1] >> 16 : raw[q >> 1] & 0xffffu);
-            }
+            for (int i = 0; i < 8; ++i) db[ct] += f[i];
         }
-        // stage X: kWStage rows x K/8 chunks
-        constexpr int XC = K / 8;
-        for (int ci = tid; ci < kWStage * XC; ci += kThreads) {
-            const int row = ci / XC, ch = ci % XC;
-            const int64_t r = r0 + row;
-            const int k = 8 * ch;
-            const uint16_t* src = k < D ? Xs + r * D + k : Xn + r * D + (k - D);
-            u32x4 raw = r < r_end ? *(const u32x4*)src : u32x4{0u, 0u, 0u, 0u};
-            #pragma unroll
-            for (int q = 0; q < 8; ++q)
-                Xt[(k + q) * P + row] = (uint16_t)(q & 1 ? raw[q >> 1] >> 16 : raw[q >> 1] & 0xffffu);
-        }
-        __syncthreads();
         #pragma unroll
-        for (int i = 0; i < TPW; ++i) {
-            const int tau = wv * TPW + i;
-            const int ct = tau & 3, kt = tau >> 2;
+        for (int kt = 0; kt < KT; ++kt) b[kt] = transpose8_b16(b[kt], lane);
+        #pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
             #pragma unroll
-            for (int rs = 0; rs < kWStage / 32; ++rs) {
-                const u32x4 a = *(const u32x4*)(dZt + (16 * ct + l16) * P + 32 * rs + 8 * g);
-                const u32x4 b = *(const u32x4*)(Xt + (16 * kt + l16) * P + 32 * rs + 8 * g);
-                acc[i] = mfma(a, b, acc[i]);
+            for (int kt = 0; kt < KT; ++kt) acc[ct][kt] = mfma(a[ct], b[kt], acc[ct][kt]);
+    }
+    // bias: lanes l16, l16 + 16, + 32, + 48 hold rows of the same channel
+    #pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+        db[ct] += __shfl_xor(db[ct], 16);
+        db[ct] += __shfl_xor(db[ct], 32);
+    }
+    // add the wavefronts' tiles in wavefront order
+    for (int w = 0; w < kWaves; ++w) {
+        if (wv == w) {
+            #pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+                #pragma unroll
+                for (int kt = 0; kt < KT; ++kt) {
+                    floatx4& dst = red[ct * KT + kt][lane];
+                    dst = w == 0 ? acc[ct][kt] : dst + acc[ct][kt];
+                }
+                if (lane < 16) redb[ct][lane] = w == 0 ? db[ct] : redb[ct][lane] + db[ct];
             }
         }
         __syncthreads();
     }
     float* pw = part + (int64_t)blockIdx.x * stride;
-    #pragma unroll
-    for (int i = 0; i < TPW; ++i) {
-        const int tau = wv * TPW + i;
-        const int ct = tau & 3, kt = tau >> 2;
+    for (int t = wv; t < CT * KT; t += kWaves) {
+        const int ct = t / KT, kt = t % KT;
         const int k = 16 * kt + l16;
-        *(floatx4*)(pw + k * kHidden + 16 * ct + 4 * g) = acc[i];
+        *(floatx4*)(pw + k * kHidden + 16 * ct + 4 * g) = red[t][lane];
     }
-    // bias: threads with equal tid % 8 own the same eight channels
-    #pragma unroll
-    for (int q = 0; q < 8; ++q) red[tid >> 3][8 * (tid & 7) + q] = db[q];
-    __syncthreads();
-    if (tid < kHidden) {
-        float s = 0.0f;
-        for (int j = 0; j < kThreads / 8; ++j) s += red[j][tid];
-        pw[K * kHidden + tid] = s;
-    }
+    if (tid < kHidden) pw[K * kHidden + tid] = redb[tid >> 4][tid & 15];
 }
 
 // out[i] = sum over blk of part[blk * stride + i], i < count, in a fixed
