@@ -281,18 +281,23 @@ def main(argv=None) -> int:
                     help="evaluate sigma(S + v) by full simulations instead of from the stored state of S")
     ap.add_argument("--methods", default="surrogate,degree_ranked,random_ranked,heuristics,celf",
                     help="selection methods to run (comma-separated)")
+    ap.add_argument("--weighting", default="wc", choices=["wc", "tv"],
+                    help="arc probabilities: weighted cascade 1/indeg(v), or trivalency (each arc one of "
+                         "0.1, 0.01, 0.001, seeded), the paper's Section 4 weightings")
     args = ap.parse_args(argv)
     os.makedirs(args.out, exist_ok=True)
     log = lambda *a: print(*a, flush=True)
     torch.cuda.set_device(0)
     g, wc = synth.chung_lu_wc_200k()
+    if args.weighting == "tv":
+        wc = synth.trivalency(g, seed=106)
     deg = g.outdeg().astype(np.int64)
     G = Graph(g.n, g.offsets, g.indices, "ic", wc)
     if args.stage == "step-bench":
         return step_bench(g, wc, args.batch, log)
     data_path = os.path.join(args.out, "pairs.npz")
     ck_path = os.path.join(args.out, "surrogate.npz")
-    report = {"graph": {"n": g.n, "m": g.m, "sha256": g.sha256()}}
+    report = {"graph": {"n": g.n, "m": g.m, "sha256": g.sha256()}, "weighting": args.weighting}
     if args.stage in ("data", "all"):
         d = generate_dataset(G, deg, args.pairs, args.data_trials, rng_seed=7, sample_seed=8, log=log)
         np.savez(data_path, offs=d["offs"], nodes=d["nodes"], sigma=d["sigma"], trials=d["trials"])

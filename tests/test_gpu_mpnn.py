@@ -6,6 +6,8 @@ alone (bf16 output: within one rounding of the fp64 value, plus fp32
 accumulation slack).  End to end: predictions and gradients against the fp64
 reference run with bf16-rounded weights and no intermediate rounding.
 """
+import sys
+
 import numpy as np
 import pytest
 
@@ -325,10 +327,16 @@ def test_trained_network_ranking_beats_the_pipeline_without_it():
                                   deg=deg, tol=None)
     rnd = surrogate.guided_greedy(G, k, R, 5, surrogate.random_scorer(3), pool_deg=256, pool_score=256, r=2, deg=deg,
                                   tol=None)
+    dgr = surrogate.guided_greedy(G, k, R, 5, surrogate.degree_scorer(deg), pool_deg=256, pool_score=256, r=2, deg=deg,
+                                  tol=None)
     j_net = surrogate.judge(G, net["seeds"], 4000, 999)
     j_rnd = surrogate.judge(G, rnd["seeds"], 4000, 999)
-    say = lambda *x: print(*x, flush=True)
-    say(f"[surrogate gain] network-ranked {j_net:.1f} vs random-ranked {j_rnd:.1f}")
+    j_dgr = surrogate.judge(G, dgr["seeds"], 4000, 999)
+    say = lambda *x: print(*x, file=sys.stderr, flush=True)
+    # the degree-ranked pipeline is reported, not asserted against: on
+    # weighted-cascade graphs with strong hubs degree order is already close
+    # to greedy's choice
+    say(f"[surrogate gain] network-ranked {j_net:.1f} vs random-ranked {j_rnd:.1f}, degree-ranked {j_dgr:.1f}")
     assert j_net > 1.05 * j_rnd
     S.close()
     G.close()
