@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "imsim.h"
+#include "plan.hpp"
 #include "sim_kernels.hpp"
 
 namespace {
@@ -123,8 +124,16 @@ struct ims_graph {
     // sets mode (ims_simulate_sets): per-slot state
     Buf sA, sN, sQ[3], sact, sstamp, ssteps, sets_dev;
     imsim::BatchItem* d_item = nullptr;  // the single-run slot form's item
-    imsim::BatchItem* h_item = nullptr;  // its pinned host staging copy
-    hipEvent_t item_copied = nullptr;    // the last upload of h_item has completed
+    // Per-call host data (seed lists, set lists, the slot item) reaches the
+    // device from pinned staging memory owned by the handle: such a copy
+    // reads its source after the call has returned, so a stage is refilled
+    // only once the previous copy out of it has completed (its event).
+    struct Stage {
+        void* h = nullptr;
+        size_t bytes = 0;
+        hipEvent_t done = nullptr;
+    };
+    Stage st_seeds, st_pre, st_setoff, st_setnodes, st_item;
     bool sets_zero_dirty = true;  // sA / sN / sstamp / ssteps must start zeroed
     bool zero_dirty = true;  // N / aux must be zero between runs
     uint32_t* d_qcount = nullptr;
@@ -180,8 +189,11 @@ struct ims_graph {
         dev_free(d_seed_pre);
         dev_free(d_status);
         if (h_flag) (void)hipHostFree(h_flag);
-        if (h_item) (void)hipHostFree(h_item);
-        if (item_copied) (void)hipEventDestroy(item_copied);
+        for (Stage* st : {&st_seeds, &st_pre, &st_setoff, &st_setnodes, &st_item}) {
+            if (st->done) (void)hipEventSynchronize(st->done);
+            if (st->h) (void)hipHostFree(st->h);
+            if (st->done) (void)hipEventDestroy(st->done);
+        }
     }
 };
 
@@ -203,6 +215,26 @@ int ensure_buf(ims_graph* g, ims_graph::Buf& b, uint64_t bytes, bool zero_invari
     b.p = p;
     b.bytes = std::max<uint64_t>(bytes, 8);
     if (zero_invariant) g->zero_dirty = true;
+    return IMS_OK;
+}
+
+// Copy `bytes` of host data to device `dst` on stream s through stage `st`
+// (see ims_graph::Stage).
+int stage_upload(ims_graph::Stage& st, void* dst, const void* src, size_t bytes, hipStream_t s)
+{
+    if (bytes == 0) return IMS_OK;
+    if (!st.done) IMS_HIP(hipEventCreateWithFlags(&st.done, hipEventDisableTiming));
+    else IMS_HIP(hipEventSynchronize(st.done));
+    if (st.bytes < bytes) {
+        if (st.h) (void)hipHostFree(st.h);
+        st.h = nullptr;
+        st.bytes = 0;
+        IMS_HIP(hipHostMalloc(&st.h, bytes, hipHostMallocDefault));
+        st.bytes = bytes;
+    }
+    std::memcpy(st.h, src, bytes);
+    IMS_HIP(hipMemcpyAsync(dst, st.h, bytes, hipMemcpyHostToDevice, s));
+    IMS_HIP(hipEventRecord(st.done, s));
     return IMS_OK;
 }
 
@@ -277,40 +309,13 @@ int ims_graph_create(int64_t n, int64_t m, const int64_t* offsets, const uint32_
     }
     if (max_deg >= (1ull << 30)) return fail(IMS_E_UNSUPPORTED, "out-degree %llu above 2^30", (unsigned long long)max_deg);
 
-    // LT: check the in-weight bound and build the in-CSR; a weight of exactly
-    // 2^32 is stored as two pieces of 2^31 so every piece fits 32 bits, and
-    // zero weights are dropped (they never add to a sum).
-    std::vector<int64_t> in_off;
-    std::vector<uint64_t> in_arc;
+    // LT: check the in-weight bound and build the in-CSR (plan.hpp)
+    imsim_plan::LtInCsr lt_in;
     if (model == IMS_MODEL_LT) {
-        const uint64_t* w64 = (const uint64_t*)param;
-        std::vector<uint64_t> wsum((size_t)std::max<int64_t>(n, 1), 0);
-        std::vector<int64_t> cnt((size_t)n + 1, 0);
-        for (int64_t e = 0; e < m; ++e) {
-            const uint64_t w = w64[e];
-            if (w > (1ull << 32)) return fail(IMS_E_WEIGHT_SUM, "LT weight of arc %lld above 2^32", (long long)e);
-            const uint32_t v = indices[e];
-            wsum[v] += w;
-            if (wsum[v] > (1ull << 32)) return fail(IMS_E_WEIGHT_SUM, "LT in-weights of node %u sum above 2^32", v);
-            cnt[v + 1] += w == 0 ? 0 : (w == (1ull << 32) ? 2 : 1);
-        }
-        in_off.assign((size_t)n + 1, 0);
-        for (int64_t v = 0; v < n; ++v) in_off[v + 1] = in_off[v] + cnt[v + 1];
-        const int64_t mi = in_off[n];
-        in_arc.resize((size_t)std::max<int64_t>(mi, 1));
-        std::vector<int64_t> pos(in_off.begin(), in_off.end() - 1);
-        for (int64_t u = 0; u < n; ++u)
-            for (int64_t e = offsets[u]; e < offsets[u + 1]; ++e) {
-                const uint64_t w = w64[e];
-                if (w == 0) continue;
-                const uint32_t v = indices[e];
-                if (w == (1ull << 32)) {
-                    in_arc[pos[v]++] = (uint64_t)u | ((uint64_t)(1u << 31) << 32);
-                    in_arc[pos[v]++] = (uint64_t)u | ((uint64_t)(1u << 31) << 32);
-                } else {
-                    in_arc[pos[v]++] = (uint64_t)u | (w << 32);
-                }
-            }
+        int64_t bad_arc = -1, bad_node = -1;
+        const int r = imsim_plan::build_lt_in_csr(n, m, offsets, indices, (const uint64_t*)param, lt_in, bad_arc, bad_node);
+        if (r == 1) return fail(IMS_E_WEIGHT_SUM, "LT weight of arc %lld above 2^32", (long long)bad_arc);
+        if (r == 2) return fail(IMS_E_WEIGHT_SUM, "LT in-weights of node %lld sum above 2^32", (long long)bad_node);
     }
 
     ims_graph* g = new (std::nothrow) ims_graph();
@@ -334,26 +339,13 @@ int ims_graph_create(int64_t n, int64_t m, const int64_t* offsets, const uint32_
         if ((rc = dev_alloc(&g->d_thr, (uint64_t)m))) return bail(rc);
         if (m > 0 && hipMemcpy(g->d_thr, param, sizeof(uint32_t) * m, hipMemcpyHostToDevice) != hipSuccess)
             return bail(fail(IMS_E_HIP, "threshold upload failed"));
-        // pull side: for every node its in-arcs in out-CSR order, each with
-        // its source and its out-CSR id (coins are keyed by that id, so a
-        // pulled arc draws the coin its push would) and threshold; arcs with
-        // threshold 0 never fire and are left out
-        const uint32_t* thr = (const uint32_t*)param;
-        std::vector<int64_t> ioff((size_t)n + 1, 0);
-        for (int64_t e = 0; e < m; ++e)
-            if (thr[e] != 0) ++ioff[(size_t)indices[e] + 1];
-        for (int64_t v = 0; v < n; ++v) ioff[v + 1] += ioff[v];
+        // pull side: per node its in-arcs with their out-CSR ids (plan.hpp)
+        imsim_plan::IcInCsr ic_in;
+        imsim_plan::build_ic_in_csr(n, m, offsets, indices, (const uint32_t*)param, ic_in);
+        const std::vector<int64_t>& ioff = ic_in.off;
+        const std::vector<uint64_t>& isa = ic_in.sa;
+        const std::vector<uint32_t>& ithr = ic_in.thr;
         const int64_t mi = ioff[n];
-        std::vector<uint64_t> isa((size_t)std::max<int64_t>(mi, 1));
-        std::vector<uint32_t> ithr((size_t)std::max<int64_t>(mi, 1));
-        std::vector<int64_t> pos(ioff.begin(), ioff.end() - 1);
-        for (int64_t u = 0; u < n; ++u)
-            for (int64_t e = offsets[u]; e < offsets[u + 1]; ++e) {
-                if (thr[e] == 0) continue;
-                const int64_t k = pos[indices[e]]++;
-                isa[k] = (uint64_t)u | ((uint64_t)e << 32);
-                ithr[k] = thr[e];
-            }
         g->ic_in_m = mi;
         double psum = 0.0;
         for (int64_t k = 0; k < mi; ++k) psum += ithr[k] == 0xFFFFFFFFu ? 1.0 : std::ldexp((double)ithr[k], -32);
@@ -366,47 +358,22 @@ int ims_graph_create(int64_t n, int64_t m, const int64_t* offsets, const uint32_
                         hipMemcpy(g->d_ic_in_thr, ithr.data(), sizeof(uint32_t) * mi, hipMemcpyHostToDevice) != hipSuccess)))
             return bail(fail(IMS_E_HIP, "IC in-CSR upload failed"));
     } else {
+        const std::vector<int64_t>& in_off = lt_in.off;
+        const std::vector<uint64_t>& in_arc = lt_in.arc;
         const int64_t mi = in_off[n];
         if ((rc = dev_alloc(&g->d_in_off, (uint64_t)n + 1))) return bail(rc);
         if ((rc = dev_alloc(&g->d_in_arc, (uint64_t)mi))) return bail(rc);
-        // uniform-weight form: every node's pieces equal
-        std::vector<uint32_t> node_w((size_t)std::max<int64_t>(n, 1), 0), src32((size_t)std::max<int64_t>(mi, 1), 0);
-        bool uniform = true;
-        for (int64_t v = 0; v < n && uniform; ++v)
-            for (int64_t k = in_off[v]; k < in_off[v + 1]; ++k) {
-                const uint32_t piece = (uint32_t)(in_arc[k] >> 32);
-                if (k == in_off[v]) node_w[v] = piece;
-                else if (piece != node_w[v]) { uniform = false; break; }
-            }
+        // equal in-weights form (every node's pieces equal) with its
+        // count-threshold planes
+        std::vector<uint32_t> node_w, src32;
+        const bool uniform = imsim_plan::lt_uniform_form(n, lt_in, node_w, src32);
         g->lt_uniform = uniform;
-        // count-threshold planes per node: the fewest S with 2^S - 1 above
-        // every count the node can reach (its in-arc pieces, at most 64 for
-        // the nodes that use the table; 0 planes for the others, 1 for a node
-        // without in-arcs)
-        // (the first plane is kept in 32 bits: a table within its memory
-        // budget has fewer than 2^32 planes per word)
         if (uniform) {
-            std::vector<uint32_t> kinfo(2 * ((size_t)n + 1), 0);
-            uint64_t planes_total = 0;
-            for (int64_t v = 0; v <= n; ++v) {
-                kinfo[2 * v] = (uint32_t)in_off[v];
-                kinfo[2 * v + 1] = (uint32_t)planes_total;
-                if (v == n) break;
-                const int64_t d = in_off[v + 1] - in_off[v];
-                uint32_t planes = 0;
-                if (d <= 64) {
-                    planes = 1;
-                    while (((1ll << planes) - 1) <= d) ++planes;
-                }
-                planes_total += planes;
-            }
-            g->kplanes_total = planes_total;
+            std::vector<uint32_t> kinfo;
+            g->kplanes_total = imsim_plan::lt_count_planes(n, in_off, kinfo);
             if ((rc = dev_alloc(&g->d_kinfo, kinfo.size()))) return bail(rc);
             if (hipMemcpy(g->d_kinfo, kinfo.data(), sizeof(uint32_t) * kinfo.size(), hipMemcpyHostToDevice) != hipSuccess)
                 return bail(fail(IMS_E_HIP, "in-CSR upload failed"));
-        }
-        if (uniform) {
-            for (int64_t k = 0; k < mi; ++k) src32[k] = (uint32_t)in_arc[k];
             if ((rc = dev_alloc(&g->d_in_src32, (uint64_t)mi))) return bail(rc);
             if ((rc = dev_alloc(&g->d_node_w, (uint64_t)n))) return bail(rc);
             if ((mi > 0 && hipMemcpy(g->d_in_src32, src32.data(), sizeof(uint32_t) * mi, hipMemcpyHostToDevice) != hipSuccess) ||
@@ -416,37 +383,13 @@ int ims_graph_create(int64_t n, int64_t m, const int64_t* offsets, const uint32_
         if (hipMemcpy(g->d_in_off, in_off.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice) != hipSuccess ||
             (mi > 0 && hipMemcpy(g->d_in_arc, in_arc.data(), sizeof(uint64_t) * mi, hipMemcpyHostToDevice) != hipSuccess))
             return bail(fail(IMS_E_HIP, "in-CSR upload failed"));
-        // node batches for the grid-shape sweep: at most 8 consecutive nodes
-        // whose in-arcs fit one 64-arc chunk; a node with more arcs is alone
-        std::vector<uint32_t> bfirst(1, 0);
-        uint32_t bcnt = 0;
-        uint64_t barcs = 0;
-        for (int64_t v = 0; v < n; ++v) {
-            const uint64_t d = (uint64_t)(in_off[v + 1] - in_off[v]);
-            if (bcnt > 0 && (bcnt == 8 || barcs + d > 64)) {
-                bfirst.push_back((uint32_t)v);
-                bcnt = 0;
-                barcs = 0;
-            }
-            ++bcnt;
-            barcs += d;
-            if (d > 64) {
-                bfirst.push_back((uint32_t)(v + 1));
-                bcnt = 0;
-                barcs = 0;
-            }
-        }
-        if (bcnt > 0) bfirst.push_back((uint32_t)n);
-        g->nbatch = (uint32_t)(bfirst.size() - 1);
-        std::vector<uint32_t> bdesc((size_t)g->nbatch * 4 + 4, 0), bigb;
-        for (uint32_t b = 0; b < g->nbatch; ++b) {
-            const int64_t a0 = in_off[bfirst[b]], pieces = in_off[bfirst[b + 1]] - a0;
-            if (pieces > 64) bigb.push_back(b);
-            bdesc[4 * b] = bfirst[b];
-            bdesc[4 * b + 1] = (bfirst[b + 1] - bfirst[b]) | ((uint32_t)std::min<int64_t>(pieces, 0xFFFFFF) << 8);
-            bdesc[4 * b + 2] = (uint32_t)a0;
-            bdesc[4 * b + 3] = (uint32_t)((uint64_t)a0 >> 32);
-        }
+        // node batches of the grid-shape sweep
+        imsim_plan::LtBatches lb;
+        imsim_plan::lt_batches(n, in_off, lb);
+        const std::vector<uint32_t>& bfirst = lb.bfirst;
+        const std::vector<uint32_t>& bdesc = lb.bdesc;
+        std::vector<uint32_t> bigb = lb.bigb;
+        g->nbatch = lb.nbatch;
         if ((rc = dev_alloc(&g->d_bfirst, bfirst.size()))) return bail(rc);
         if ((rc = dev_alloc(&g->d_bdesc, bdesc.size()))) return bail(rc);
         g->nbig = (uint32_t)bigb.size();
@@ -619,8 +562,6 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
             g->sets_zero_dirty = false;
         }
         if (!g->d_item && (rc = dev_alloc(&g->d_item, 1))) return rc;
-        if (!g->h_item) IMS_HIP(hipHostMalloc((void**)&g->h_item, sizeof(imsim::BatchItem), hipHostMallocDefault));
-        if (!g->item_copied) IMS_HIP(hipEventCreateWithFlags(&g->item_copied, hipEventDisableTiming));
     }
     if (!active_bits && !slot_run && (rc = ensure_buf(g, g->A, cells * 8, false))) return rc;
     if (shape == 1 && !slot_run) {
@@ -674,8 +615,8 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
     std::vector<uint64_t> seed_pre(sv.size() + 1, 0);
     for (size_t i = 0; i < sv.size(); ++i) seed_pre[i + 1] = seed_pre[i] + (uint64_t)(g->h_off[sv[i] + 1] - g->h_off[sv[i]]);
     if (!g->h_flag) IMS_HIP(hipHostMalloc((void**)&g->h_flag, 4 * sizeof(uint32_t), hipHostMallocDefault));
-    if (!sv.empty()) IMS_HIP(hipMemcpyAsync(g->d_seeds, sv.data(), sv.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
-    IMS_HIP(hipMemcpyAsync(g->d_seed_pre, seed_pre.data(), seed_pre.size() * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+    if ((rc = stage_upload(g->st_seeds, g->d_seeds, sv.data(), sv.size() * sizeof(uint32_t), s))) return rc;
+    if ((rc = stage_upload(g->st_pre, g->d_seed_pre, seed_pre.data(), seed_pre.size() * sizeof(uint64_t), s))) return rc;
 
     uint64_t* A = active_bits ? active_bits : (uint64_t*)g->A.p;
     // the LT grid shape keeps its state node-major and writes A (when asked
@@ -759,18 +700,14 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
     }
     if (slot_run) {
         if (node_counts && (rc = fill_async<uint32_t>(node_counts, n, 0u, s))) return rc;
-        // the item goes up from pinned memory, which the previous call's
-        // upload must have finished reading before it is overwritten
-        IMS_HIP(hipEventSynchronize(g->item_copied));
-        imsim::BatchItem& it = *g->h_item;
+        imsim::BatchItem it;
         std::memset(&it, 0, sizeof it);
         it.P = P;
         it.model = g->model;
         it.trial_counts = trial_counts;
         it.node_counts = node_counts;
         it.total = total;
-        IMS_HIP(hipMemcpyAsync(g->d_item, g->h_item, sizeof it, hipMemcpyHostToDevice, s));
-        IMS_HIP(hipEventRecord(g->item_copied, s));
+        if ((rc = stage_upload(g->st_item, g->d_item, &it, sizeof it, s))) return rc;
         imsim::SlotBufs S{n,
                           (uint64_t*)g->sA.p,
                           (uint64_t*)g->sN.p,
@@ -1009,8 +946,8 @@ int simulate_sets_impl(ims_graph* g, const uint64_t* base, const uint32_t* set_o
     if ((rc = ensure_buf(g, g->sets_dev, set_bytes, false))) return rc;
     uint32_t* d_off = (uint32_t*)g->sets_dev.p;
     uint32_t* d_nodes = d_off + off.size();
-    IMS_HIP(hipMemcpyAsync(d_off, off.data(), off.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
-    if (!nodes.empty()) IMS_HIP(hipMemcpyAsync(d_nodes, nodes.data(), nodes.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    if ((rc = stage_upload(g->st_setoff, d_off, off.data(), off.size() * sizeof(uint32_t), s))) return rc;
+    if ((rc = stage_upload(g->st_setnodes, d_nodes, nodes.data(), nodes.size() * sizeof(uint32_t), s))) return rc;
 
     // slot state starts clear: fresh buffers are cleared once, and every task
     // clears what it touched (the rows of the nodes it activated, its next-
