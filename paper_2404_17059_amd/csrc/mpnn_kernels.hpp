@@ -56,6 +56,35 @@ __device__ __forceinline__ floatx4 mfma(const u32x4& a, const u32x4& b, floatx4 
                                                    0);
 }
 
+// A wavefront's 16 x 64 bf16 output tile goes through LDS so that its rows,
+// which lie contiguously in memory, are stored 16 bytes per lane: the MFMA
+// result gives each lane 8 bytes of one row only.  kTilePitch: LDS words per
+// staged row (64 bf16 + 4 words, keeping 16-byte alignment).
+constexpr int kTilePitch = 36;
+
+// Lane (l16, g) puts the four values of channels c .. c+3 of row l16.
+__device__ __forceinline__ void tile_put(uint32_t* tile, int l16, int c, float y0, float y1, float y2, float y3)
+{
+    *(u32x2*)(tile + l16 * kTilePitch + c / 2) = u32x2{pack2(y0, y1), pack2(y2, y3)};
+}
+
+// Stores the staged tile as rows row0 .. row0 + 15 of Y ([R][64]); only this
+// wavefront touched `tile`, and LDS operations of one wavefront complete in
+// order, so no barrier is needed.
+__device__ __forceinline__ void tile_store(const uint32_t* tile, uint16_t* __restrict__ Y, int64_t row0, int64_t R, int lane)
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    #pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int c = 64 * j + lane;  // 16-byte piece c of the tile: row c / 8, piece c % 8
+        const int r = c >> 3, pc = c & 7;
+        const u32x4 v = *(const u32x4*)(tile + r * kTilePitch + 4 * pc);
+        if (row0 + r < R) *(u32x4*)(Y + (row0 + r) * kHidden + 8 * pc) = v;
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
 // ---------------------------------------------------------------------------
 // Input features.  Row r = v*B + b gets [s, f1(v), f2(v), f3(v), 0 ...] with
 // s = 0; a second kernel sets s = 1 for the members of each set.
@@ -229,6 +258,8 @@ __global__ void __launch_bounds__(kThreads) dense_fwd_kernel(int64_t R, const ui
     constexpr int KS = K / 32;      // MFMA k-steps
     constexpr int P = K + 8;        // LDS pitch (bf16) of W^T rows
     __shared__ uint16_t Wt[kHidden * P];
+    __shared__ __attribute__((aligned(16))) uint32_t Ytile[kThreads / 64][16 * kTilePitch];
+    uint32_t* tile = Ytile[threadIdx.x >> 6];
     for (int i = threadIdx.x; i < K * kHidden; i += kThreads) {
         const int k = i / kHidden, c = i % kHidden;
         Wt[c * P + k] = (uint16_t)f2bf(W[i]);
@@ -277,16 +308,15 @@ __global__ void __launch_bounds__(kThreads) dense_fwd_kernel(int64_t R, const ui
             #pragma unroll
             for (int ks = 0; ks < KS; ++ks) acc[ct] = mfma(A[ct][ks], Bf[ks], acc[ct]);
         }
-        if (ok) {
+        (void)ok;
+        #pragma unroll
+        for (int ct = 0; ct < 4; ++ct) {
+            float y[4];
             #pragma unroll
-            for (int ct = 0; ct < 4; ++ct) {
-                float y[4];
-                #pragma unroll
-                for (int q = 0; q < 4; ++q) y[q] = fmaxf(acc[ct][q] + bv[ct][q], 0.0f);
-                u32x2 o = {pack2(y[0], y[1]), pack2(y[2], y[3])};
-                *(u32x2*)(Y + row * kHidden + 16 * ct + 4 * g) = o;
-            }
+            for (int q = 0; q < 4; ++q) y[q] = fmaxf(acc[ct][q] + bv[ct][q], 0.0f);
+            tile_put(tile, l16, 16 * ct + 4 * g, y[0], y[1], y[2], y[3]);
         }
+        tile_store(tile, Y, t * 16, R, lane);
     }
 }
 
@@ -304,6 +334,9 @@ __global__ void __launch_bounds__(kThreads) dense_bwd_data_kernel(int64_t R, con
     constexpr int KT = K / 16;       // 16-wide tiles of the output columns
     constexpr int P = kHidden + 8;   // LDS pitch of W rows
     __shared__ uint16_t Wb[K * P];
+    static_assert(D == kHidden, "the staged output tiles hold rows of 64 values");
+    __shared__ __attribute__((aligned(16))) uint32_t Otile[kThreads / 64][2][16 * kTilePitch];
+    uint32_t* otile = Otile[threadIdx.x >> 6][0];
     for (int i = threadIdx.x; i < K * kHidden; i += kThreads) Wb[(i / kHidden) * P + i % kHidden] = (uint16_t)f2bf(W[i]);
     __syncthreads();
     const int lane = threadIdx.x & 63;
@@ -332,18 +365,17 @@ __global__ void __launch_bounds__(kThreads) dense_bwd_data_kernel(int64_t R, con
         const bool ok = row < R;
         u32x4 Bf[2] = {Bn[0], Bn[1]};
         load(t + waves, Bn);
+        (void)ok;
         #pragma unroll
         for (int kt = 0; kt < KT; ++kt) {
             floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
             acc = mfma(A[kt][0], Bf[0], acc);
             acc = mfma(A[kt][1], Bf[1], acc);
-            if (ok) {
-                const int k = 16 * kt + 4 * g;
-                u32x2 o = {pack2(acc[0], acc[1]), pack2(acc[2], acc[3])};
-                uint16_t* dst = k < D ? dXs + row * D + k : dXn + row * D + (k - D);
-                *(u32x2*)dst = o;
-            }
+            const int k = 16 * kt + 4 * g;
+            tile_put(otile + (k < D ? 0 : 16 * kTilePitch), l16, k < D ? k : k - D, acc[0], acc[1], acc[2], acc[3]);
         }
+        tile_store(otile, dXs, t * 16, R, lane);
+        tile_store(otile + 16 * kTilePitch, dXn, t * 16, R, lane);
     }
 }
 
