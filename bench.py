@@ -41,7 +41,11 @@ def load_workload(name: str):
     if name in WORKLOADS:
         return getattr(synth, WORKLOADS[name])()
     return synth.paper_ic_suite()[SUITE.index(name[len("paper_"):])]
-KERNEL_SOURCES = ["paper_2404_17059_amd/csrc/sim_kernels.hpp", "paper_2404_17059_amd/csrc/philox.hpp"]
+# every source that decides what the simulation kernels do and how they are
+# launched (grid sizes, padding, threshold form): a measured traffic figure is
+# reported only while all of them are unchanged
+KERNEL_SOURCES = ["paper_2404_17059_amd/csrc/sim_kernels.hpp", "paper_2404_17059_amd/csrc/philox.hpp",
+                  "paper_2404_17059_amd/csrc/imsim.hip"]
 
 
 def log(*a):
@@ -80,7 +84,18 @@ def load_traffic(workload: str):
     return d
 
 
-def cpu_baseline(w, sample_trials: int, threads: int) -> dict:
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_rate(w, sample_trials: int, threads: int) -> dict:
     import oracle
     enc = oracle.encode(w.model, w.param)
     t0 = time.perf_counter()
@@ -88,9 +103,29 @@ def cpu_baseline(w, sample_trials: int, threads: int) -> dict:
                         w.rng_seed, threads=threads, want_bits=False, want_node_counts=False)
     dt = time.perf_counter() - t0
     exams = int(r["exams"].sum())
-    return {"value": exams / dt, "unit": "edge-examinations/s", "cores": threads, "kind": "oracle",
-            "sample": f"trials 0..{sample_trials - 1} of {w.n_trials} of the same workload (same graph, seeds, rng_seed)",
-            "trials_per_sec": sample_trials / dt, "seconds": round(dt, 3)}
+    return {"value": exams / dt, "trials_per_sec": sample_trials / dt, "seconds": round(dt, 3),
+            "trials": sample_trials, "threads": threads}
+
+
+def cpu_baseline(w, sample_all: int, sample_one: int) -> dict:
+    """The oracle on the host: trial-parallel on every core this process may
+    use (the affinity set, capped by OMP_NUM_THREADS when that is set, as on a
+    host shared per GPU), and on one thread; each on a bounded sample of the
+    workload's trials (same graph, seeds and rng_seed)."""
+    visible = len(os.sched_getaffinity(0))
+    share = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    threads = min(visible, share) if share > 0 else visible
+    log(f"[bench] cpu_baseline: oracle on {sample_all} trials x {threads} threads, then {sample_one} trials x 1 thread")
+    allc = oracle_rate(w, sample_all, threads)
+    one = oracle_rate(w, sample_one, 1)
+    return {"value": allc["value"], "unit": "edge-examinations/s", "cores": threads, "kind": "oracle",
+            "sample": f"trials 0..{sample_all - 1} of {w.n_trials} of the same workload (same graph, seeds, rng_seed); "
+                      f"one-thread leg on trials 0..{sample_one - 1}",
+            "trials_per_sec": allc["trials_per_sec"], "seconds": allc["seconds"],
+            "one_thread": {"value": one["value"], "trials_per_sec": one["trials_per_sec"], "seconds": one["seconds"],
+                           "trials": sample_one},
+            "cpu_model": cpu_model(), "host_cpus_visible": visible,
+            "omp_num_threads": share or None}
 
 
 def copy_calibration(mib: int) -> int:
@@ -117,7 +152,11 @@ def run_suite(args) -> int:
     import synth
 
     rows, tot_exams, tot_s, tot_trials = [], 0, 0.0, 0
-    for w in synth.paper_ic_suite():
+    opts = ims.Opts(shape=args.shape, ic_direction={"auto": 0, "push": 1, "pull": 2}[args.ic_direction])
+    suite = synth.paper_ic_suite()
+    if args.with_c1c2:
+        suite = suite + [synth.er_ic_1k(), synth.ba_ic_100k()]
+    for w in suite:
         g = w.graph
         G = ims.Graph(g.n, g.offsets, g.indices, w.model, w.param)
         T = w.n_trials
@@ -126,17 +165,19 @@ def run_suite(args) -> int:
         tot = torch.empty(1, dtype=torch.int64, device=dev)
         nc = torch.empty(g.n, dtype=torch.int32, device=dev)
         for _ in range(args.warmup):
-            ims.simulate_into(G, w.seeds, T, w.rng_seed, tc, tot, nc)
+            ims.simulate_into(G, w.seeds, T, w.rng_seed, tc, tot, nc, opts=opts)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            ims.simulate_into(G, w.seeds, T, w.rng_seed, tc, tot, nc)
+            ims.simulate_into(G, w.seeds, T, w.rng_seed, tc, tot, nc, opts=opts)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.steps
+        dirs = G.level_directions()
         counts = nc.cpu().numpy().view(np.uint32).astype(np.int64)
         exams = int((counts * g.outdeg()).sum())
         rows.append({"workload": w.name, "n": g.n, "m": g.m, "ms": round(dt * 1e3, 4), "mean_spread": int(tot.item()) / T,
-                     "exams_per_s": exams / dt, "trials_per_s": T / dt})
+                     "exams_per_s": exams / dt, "trials_per_s": T / dt,
+                     "levels_pulled": f"{int((dirs == 2).sum())}/{len(dirs)}" if len(dirs) else None})
         tot_exams += exams
         tot_s += dt
         tot_trials += T
@@ -145,7 +186,9 @@ def run_suite(args) -> int:
     print(json.dumps({"metric": METRIC, "value": tot_exams / tot_s, "unit": "edge-examinations/s", "n_gpus": 1,
                       "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(tot_s * 1e3, 4),
                       "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
-                      "data": "synthetic", "config": {"workload": "ic_paper_suite_9x1000_trials_100_seeds"},
+                      "data": "synthetic", "config": {"workload": "ic_paper_suite_9x1000_trials_100_seeds"
+                                                      + ("_plus_er_1k_ba_100k" if args.with_c1c2 else ""),
+                                                      "shape": args.shape, "ic_direction": args.ic_direction},
                       "trials_per_sec": tot_trials / tot_s, "suite": rows}), flush=True)
     return 0
 
@@ -191,7 +234,8 @@ def run_batch(args) -> int:
                       "config": {"workload": "batch_64_items_er_ba_ic_lt_2000_trials", "items": len(ws),
                                  "sum_n": int(sum(w.graph.n for w in ws)), "sum_m": int(sum(w.graph.m for w in ws))},
                       "trials_per_sec": trials / dt, "default_ms_per_step": round(dt_default * 1e3, 4),
-                      "tuning": {"blocks_per_cu": chosen[0], "order": chosen[1], "split": chosen[2]},
+                      "tuning": {"blocks_per_cu": chosen[0], "order": chosen[1], "split": chosen[2],
+                                 "ic_alpha": chosen[3], "ic_beta": chosen[4]},
                       "mean_spreads": [r["mean"] for r in res]}), flush=True)
     B.close()
     for it in items:
@@ -206,7 +250,14 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="lt_chunglu_1m",
                     choices=sorted(WORKLOADS) + ["paper_" + x for x in SUITE] + ["paper_suite", "batch64"])
-    ap.add_argument("--cpu-sample", type=int, default=64, help="oracle trials timed for cpu_baseline (0 = skip)")
+    ap.add_argument("--cpu-sample", type=int, default=64, help="oracle trials timed on all cores for cpu_baseline (0 = skip)")
+    ap.add_argument("--cpu-sample-one", type=int, default=16, help="oracle trials timed on one thread for cpu_baseline")
+    ap.add_argument("--shape", type=int, default=0, choices=[0, 1, 2],
+                    help="paper_suite: execution shape (0 automatic, 1 word-local, 2 grid-wide)")
+    ap.add_argument("--ic-direction", default="auto", choices=["auto", "push", "pull"],
+                    help="paper_suite: IC direction (auto = the per-level rule)")
+    ap.add_argument("--with-c1c2", action="store_true",
+                    help="paper_suite: also run the 1k-node ER and 100k-node BA IC workloads")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -274,19 +325,22 @@ def main() -> int:
     roofline = None
     if alg is not None:
         achieved = alg["bytes"] / kernel_avg_s / 1e9
+        # frac: algorithmic bytes (the push traffic of the frontier expansion)
+        # per second; frac_measured: the bytes the hardware counters saw
+        measured = None if traffic is None else traffic["bytes_per_launch"] / kernel_avg_s / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": None if traffic is None else traffic["bytes_per_launch"],
+                    "achieved_measured": None if measured is None else round(measured, 1),
+                    "frac_measured": None if measured is None else round(measured / HBM_PEAK_GBS, 4),
                     "kernel": "ims_simulate call (count-threshold table, ltg_sweep_kernel sweeps, final pass)", "kernel_ms": round(kernel_avg_s * 1e3, 4),
                     "alg_bytes_per_launch": alg["bytes"], "alg_units_per_launch": alg["units"]}
 
     cpu = None
     if args.cpu_sample > 0:
         import oracle
-        threads = min(16, len(os.sched_getaffinity(0)))
         oracle.build() if not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")) else None
-        log(f"[bench] cpu_baseline: oracle on {args.cpu_sample} trials, {threads} threads")
-        cpu = cpu_baseline(w, min(args.cpu_sample, T), threads)
+        cpu = cpu_baseline(w, min(args.cpu_sample, T), min(max(args.cpu_sample_one, 1), T))
 
     rec = {
         "metric": METRIC,
