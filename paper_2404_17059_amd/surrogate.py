@@ -281,6 +281,7 @@ def main(argv=None) -> int:
                     help="evaluate sigma(S + v) by full simulations instead of from the stored state of S")
     ap.add_argument("--methods", default="surrogate,degree_ranked,random_ranked,heuristics,celf",
                     help="selection methods to run (comma-separated)")
+    ap.add_argument("--n", type=int, default=200_000, help="nodes of the Chung-Lu graph (exponent 2.3, mean degree 10)")
     ap.add_argument("--weighting", default="wc", choices=["wc", "tv"],
                     help="arc probabilities: weighted cascade 1/indeg(v), or trivalency (each arc one of "
                          "0.1, 0.01, 0.001, seeded), the paper's Section 4 weightings")
@@ -288,7 +289,7 @@ def main(argv=None) -> int:
     os.makedirs(args.out, exist_ok=True)
     log = lambda *a: print(*a, flush=True)
     torch.cuda.set_device(0)
-    g, wc = synth.chung_lu_wc_200k()
+    g, wc = synth.chung_lu_wc_200k(args.n)
     if args.weighting == "tv":
         wc = synth.trivalency(g, seed=106)
     deg = g.outdeg().astype(np.int64)
