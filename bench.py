@@ -193,6 +193,35 @@ def run_suite(args) -> int:
     return 0
 
 
+def batch_timeline(B, ws) -> dict:
+    """One more launch with per-task timing: the span from the first task's
+    start to the last task's end, how busy the workgroup slots were, and the
+    items that took the most task time (device wall clock, 100 MHz)."""
+    import torch
+    B.task_timing(True)
+    B.launch()
+    torch.cuda.synchronize()
+    codes, times = B.task_times()
+    B.task_timing(False)
+    if len(codes) == 0:
+        return {}
+    start, end, slot = times[:, 0].astype(np.int64), times[:, 1].astype(np.int64), times[:, 2].astype(np.int64)
+    t0 = int(start.min())
+    span = int(end.max()) - t0
+    busy = int((end - start).sum())
+    slots = int(slot.max()) + 1
+    item = (codes >> np.uint64(32)).astype(np.int64)
+    per_item = np.bincount(item, weights=(end - start).astype(np.float64), minlength=len(ws))
+    top = np.argsort(-per_item)[:8]
+    last_end = np.sort(end - t0)
+    return {"clock_mhz": 100, "span_ms": span / 1e5, "slots": slots, "tasks": int(len(codes)),
+            "slot_busy_frac": busy / (slots * span) if span > 0 else None,
+            "median_task_us": float(np.median(end - start)) / 100.0, "max_task_us": float((end - start).max()) / 100.0,
+            "ms_until_90pct_tasks_done": float(last_end[int(0.9 * (len(last_end) - 1))]) / 1e5,
+            "top_items": [{"item": ws[i].name, "task_ms": float(per_item[i]) / 1e5,
+                           "share": float(per_item[i] / per_item.sum())} for i in top]}
+
+
 def run_batch(args) -> int:
     """The 64-item uneven batch (IC and LT mixed, 2,000 trials each) as one
     persistent launch replayed from its HIP graph: timed with the default
@@ -225,6 +254,7 @@ def run_batch(args) -> int:
     dt = timed()
     log(f"[bench] autotuned {chosen}: {dt * 1e3:.2f} ms per launch")
     res = B.results()
+    timeline = batch_timeline(B, ws)
     exams = sum(int((r["node_counts"].astype(np.int64) * w.graph.outdeg()).sum()) for r, w in zip(res, ws))
     trials = sum(w.n_trials for w in ws)
     print(json.dumps({"metric": METRIC, "value": exams / dt, "unit": "edge-examinations/s", "n_gpus": 1,
@@ -236,7 +266,7 @@ def run_batch(args) -> int:
                       "trials_per_sec": trials / dt, "default_ms_per_step": round(dt_default * 1e3, 4),
                       "tuning": {"blocks_per_cu": chosen[0], "order": chosen[1], "split": chosen[2],
                                  "ic_alpha": chosen[3], "ic_beta": chosen[4]},
-                      "mean_spreads": [r["mean"] for r in res]}), flush=True)
+                      "mean_spreads": [r["mean"] for r in res], "timeline": timeline}), flush=True)
     B.close()
     for it in items:
         it[0].close()

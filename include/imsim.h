@@ -133,7 +133,8 @@ typedef struct ims_opts {
  *   total         device uint64[1]: sum_t |A_t|; sigma = total / T.  required
  *   active_bits   device uint64[ceil(T/64) * n], word-major.         optional (NULL)
  * Asynchronous on `stream` in the word-local shape; the grid shape reads one
- * step counter back per batch of steps and so returns after the run. */
+ * step counter back per batch of steps and so returns once its last step has
+ * run (the final pass and the status words are still in flight then). */
 int ims_simulate(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_t n_trials,
                  uint64_t rng_seed, const ims_opts* opts, uint32_t* trial_counts,
                  uint32_t* node_counts, uint64_t* total, uint64_t* active_bits, void* stream);
@@ -263,6 +264,20 @@ int ims_batch_autotune(ims_batch* b, int repeats, void* stream, ims_tuning* chos
  * it.  Asynchronous. */
 int ims_batch_launch(ims_batch* b, void* stream);
 int ims_batch_destroy(ims_batch* b);
+
+/* Per-task timeline of batch launches (inspection hook for profiles):
+ * ims_batch_task_timing(b, 1) makes every later launch record, for each task,
+ * the device wall clock (a constant-rate counter, 100 MHz on this device
+ * family) at its start and end and the workgroup slot that ran it; 0 turns
+ * it off.  Either call drops the captured HIP graph.  ims_batch_task_times
+ * waits for `stream` and copies, for the tasks of the last launch in the
+ * order they are listed, their codes (item << 32 | log2 trials-per-task
+ * split << 24 | part << 16 | word) into tasks (host uint64[max_tasks]) and
+ * (start, end, slot) into times (host uint64[3 * max_tasks]); *count =
+ * tasks written.  IMS_E_INVALID_ARG while timing is off. */
+int ims_batch_task_timing(ims_batch* b, int enable);
+int ims_batch_task_times(ims_batch* b, uint32_t max_tasks, uint64_t* tasks, uint64_t* times, uint32_t* count,
+                         void* stream);
 
 /* Status of the last run on this handle: out[0] = steps (IC frontier levels
  * or LT sweeps) taken, out[1] = nonzero if the step guard fired.  Waits for

@@ -71,6 +71,8 @@ _sig("ims_batch_create", _int, ctypes.POINTER(BatchItem), _u32, ctypes.POINTER(T
 _sig("ims_batch_autotune", _int, _P, _int, _P, ctypes.POINTER(Tuning))
 _sig("ims_batch_launch", _int, _P, _P)
 _sig("ims_batch_destroy", _int, _P)
+_sig("ims_batch_task_timing", _int, _P, _int)
+_sig("ims_batch_task_times", _int, _P, _u32, _P, _P, ctypes.POINTER(_u32), _P)
 _sig("ims_simulate_sets", _int, _P, _P, _P, _u32, _u32, _u64, ctypes.POINTER(Opts), _P, _P, _P)
 _sig("ims_simulate_levels", _int, _P, _P, _u32, _u32, _u64, _u32, _P, _P, _P, _P)
 _sig("ims_simulate_sets_from", _int, _P, _P, _P, _P, _u32, _u32, _u64, ctypes.POINTER(Opts), _P, _P, _P)
@@ -420,6 +422,19 @@ class Batch:
 
     def launch(self, stream=None) -> None:
         _check(_lib.ims_batch_launch(self._h, _stream_handle(stream)), "ims_batch_launch")
+
+    def task_timing(self, enable: bool = True) -> None:
+        """Record every task's start, end (device wall clock) and slot at later launches."""
+        _check(_lib.ims_batch_task_timing(self._h, int(bool(enable))), "ims_batch_task_timing")
+
+    def task_times(self, max_tasks: int = 1 << 22, stream=None) -> tuple[np.ndarray, np.ndarray]:
+        """(task codes uint64[k], times uint64[k, 3] = start, end, slot) of the last launch."""
+        codes = np.zeros(max(int(max_tasks), 1), dtype=np.uint64)
+        times = np.zeros((max(int(max_tasks), 1), 3), dtype=np.uint64)
+        cnt = ctypes.c_uint32()
+        _check(_lib.ims_batch_task_times(self._h, int(max_tasks), _np_ptr(codes), _np_ptr(times), ctypes.byref(cnt),
+                                         _stream_handle(stream)), "ims_batch_task_times")
+        return codes[:cnt.value], times[:cnt.value]
 
     def results(self) -> list[dict]:
         out = []

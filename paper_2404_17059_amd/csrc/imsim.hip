@@ -142,7 +142,10 @@ struct ims_graph {
     uint64_t* d_seed_pre = nullptr;  // prefix of seed out-degrees
     uint32_t seeds_cap = 0;
     uint32_t* d_status = nullptr;     // [0] steps, [1] guard, [2] task counter
-    uint32_t* h_flag = nullptr;       // pinned readback of one step counter
+    uint32_t* h_flag = nullptr;       // pinned readback of one step counter ([0]) and of the
+                                      // last grid run's status words ([2], [3])
+    hipEvent_t status_read = nullptr; // that status readback has landed
+    bool status_pending = false;      // a grid run's status readback is still to be taken in
     uint32_t last_steps = 0;          // hint for the next grid-shape run
     uint32_t last_shape = 0;
     // kernel timing ring (ims_graph_profile)
@@ -188,7 +191,9 @@ struct ims_graph {
         dev_free(d_seeds);
         dev_free(d_seed_pre);
         dev_free(d_status);
+        if (status_read) (void)hipEventSynchronize(status_read);
         if (h_flag) (void)hipHostFree(h_flag);
+        if (status_read) (void)hipEventDestroy(status_read);
         for (Stage* st : {&st_seeds, &st_pre, &st_setoff, &st_setnodes, &st_item}) {
             if (st->done) (void)hipEventSynchronize(st->done);
             if (st->h) (void)hipHostFree(st->h);
@@ -235,6 +240,19 @@ int stage_upload(ims_graph::Stage& st, void* dst, const void* src, size_t bytes,
     std::memcpy(st.h, src, bytes);
     IMS_HIP(hipMemcpyAsync(dst, st.h, bytes, hipMemcpyHostToDevice, s));
     IMS_HIP(hipEventRecord(st.done, s));
+    return IMS_OK;
+}
+
+// The last grid-shape run's status, read back without blocking that run:
+// its step count sizes the next run's step batches, and a cut-off run leaves
+// frontier masks behind that the next run must clear.
+int take_grid_status(ims_graph* g)
+{
+    if (!g->status_pending) return IMS_OK;
+    IMS_HIP(hipEventSynchronize(g->status_read));
+    g->status_pending = false;
+    g->last_steps = g->h_flag[2];
+    if (g->h_flag[3]) g->zero_dirty = true;
     return IMS_OK;
 }
 
@@ -484,6 +502,7 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
     hipStream_t s = (hipStream_t)stream;
     int rc = device_cus(g);
     if (rc) return rc;
+    if ((rc = take_grid_status(g))) return rc;
 
     // seeds: range check and set semantics on the host
     std::vector<uint32_t> sv(seeds, seeds + n_seeds);
@@ -822,26 +841,21 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
             hipLaunchKernelGGL(imsim::grid_ic_level_kernel, dim3(blocks), dim3(imsim::kBlock), 0, s, P, next);
             IMS_HIP(hipGetLastError());
         }
-        // number of steps: first step counter that is zero
-        std::vector<uint32_t> qc(std::min<uint32_t>(next + 1, g->cap));
-        IMS_HIP(hipMemcpy(qc.data(), g->d_qcount, qc.size() * sizeof(uint32_t), hipMemcpyDeviceToHost));
-        uint32_t steps = 0;
-        while (steps < next && qc[steps] != 0) ++steps;
-        if (g->model == IMS_MODEL_LT) steps += 1;
-        g->last_steps = steps;
-        if (next >= g->cap && qc.back() != 0) {
-            g->zero_dirty = true;  // a cut-off run leaves frontier masks behind
-            uint32_t one = 1;
-            IMS_HIP(hipMemcpyAsync(g->d_status + 1, &one, sizeof one, hipMemcpyHostToDevice, s));
-        }
-        IMS_HIP(hipMemcpyAsync(g->d_status, &steps, sizeof steps, hipMemcpyHostToDevice, s));
-        IMS_HIP(hipStreamSynchronize(s));
         if (g->model == IMS_MODEL_LT && cells > 0) {
             hipLaunchKernelGGL(imsim::ltg_finish_kernel, dim3((uint32_t)std::min<uint64_t>((uint64_t)g->cus * 4, ((uint64_t)g->n + 255) / 256)),
                                dim3(imsim::kBlock), 0, s, (const uint64_t*)P.Anm, active_bits, g->n, W, n_trials, trial_counts,
                                node_counts, (unsigned long long*)total, accumulate ? 1 : 0);
             IMS_HIP(hipGetLastError());
         }
+        // steps taken and the guard go into the status words on the device;
+        // the host takes them in at its next call on this handle
+        hipLaunchKernelGGL(imsim::grid_status_kernel, dim3(1), dim3(64), 0, s, (const uint32_t*)g->d_qcount, next, g->cap,
+                           g->model == IMS_MODEL_LT ? 1u : 0u, g->d_status);
+        IMS_HIP(hipGetLastError());
+        if (!g->status_read) IMS_HIP(hipEventCreateWithFlags(&g->status_read, hipEventDisableTiming));
+        IMS_HIP(hipMemcpyAsync(g->h_flag + 2, g->d_status, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        IMS_HIP(hipEventRecord(g->status_read, s));
+        g->status_pending = true;
     }
     if (prof) {
         IMS_HIP(hipEventRecord(g->prof_ev[2 * slot + 1], s));
@@ -1033,6 +1047,8 @@ struct ims_batch {
     imsim::BatchItem* d_items = nullptr;
     uint64_t* d_tasks = nullptr;
     uint32_t* d_ctl = nullptr;  // [0] task counter, [1..4] status words (steps, guard, -, refused hand-overs)
+    uint64_t* d_times = nullptr;  // per task (start, end, slot) when task timing is on (ims_batch_task_timing)
+    bool timing = false;
     ims_graph::Buf sA, sN, sQ0, sQ1, sQ2, sact, sstamp, ssteps;
     uint32_t slots = 0;
     hipGraph_t graph = nullptr;
@@ -1054,6 +1070,7 @@ struct ims_batch {
         dev_free(d_items);
         dev_free(d_tasks);
         dev_free(d_ctl);
+        dev_free(d_times);
         for (ims_graph::Buf* b : {&sA, &sN, &sQ0, &sQ1, &sQ2, &sact, &sstamp, &ssteps}) ims_graph::release(*b);
     }
 };
@@ -1097,6 +1114,7 @@ int batch_plan(ims_batch* b)
                     tasks.push_back(((uint64_t)i << 32) | ((uint64_t)s << 24) | ((uint64_t)part << 16) | w);
     }
     if (tasks.size() >= 0xFFFFFFFFull) return fail(IMS_E_UNSUPPORTED, "ims_batch: more than 2^32 - 2 tasks");
+    int rc0;
     // the tuning's IC switch points go into every item
     for (uint32_t i = 0; i < n_items; ++i) {
         int rc = set_ic_direction(b->host_items[i].P, b->items[i].graph, b->tuning.ic_alpha, b->tuning.ic_beta, 0);
@@ -1105,6 +1123,8 @@ int batch_plan(ims_batch* b)
     if (n_items > 0)
         IMS_HIP(hipMemcpy(b->d_items, b->host_items.data(), n_items * sizeof(imsim::BatchItem), hipMemcpyHostToDevice));
     b->n_tasks = (uint32_t)tasks.size();
+    dev_free(b->d_times);
+    if (b->timing && (rc0 = dev_alloc(&b->d_times, 3ull * std::max<uint32_t>(b->n_tasks, 1)))) return rc0;
     dev_free(b->d_tasks);
     int rc = dev_alloc(&b->d_tasks, tasks.size());
     if (rc) return rc;
@@ -1145,7 +1165,7 @@ int batch_enqueue(ims_batch* b, hipStream_t s)
                       (uint32_t*)b->sstamp.p,
                       (uint32_t*)b->ssteps.p};
     hipLaunchKernelGGL(imsim::batch_kernel, dim3(b->slots), dim3(imsim::kTaskBlock), 0, s, (const imsim::BatchItem*)b->d_items,
-                       (const uint64_t*)b->d_tasks, b->n_tasks, b->d_ctl, S, b->d_ctl + 1);
+                       (const uint64_t*)b->d_tasks, b->n_tasks, b->d_ctl, S, b->d_ctl + 1, b->timing ? b->d_times : nullptr);
     IMS_HIP(hipGetLastError());
     return IMS_OK;
 }
@@ -1328,6 +1348,29 @@ int ims_batch_autotune(ims_batch* b, int repeats, void* stream, ims_tuning* chos
     return IMS_OK;
 }
 
+int ims_batch_task_timing(ims_batch* b, int enable)
+{
+    if (!b) return fail(IMS_E_INVALID_ARG, "ims_batch_task_timing: NULL batch");
+    if ((enable != 0) == b->timing) return IMS_OK;
+    b->timing = enable != 0;
+    return batch_plan(b);  // (re)allocates the record and drops the captured graph
+}
+
+int ims_batch_task_times(ims_batch* b, uint32_t max_tasks, uint64_t* tasks, uint64_t* times, uint32_t* count, void* stream)
+{
+    if (!b || !count || (max_tasks > 0 && (!tasks || !times))) return fail(IMS_E_INVALID_ARG, "ims_batch_task_times: bad arguments");
+    *count = 0;
+    if (!b->timing || !b->d_times) return fail(IMS_E_INVALID_ARG, "ims_batch_task_times: task timing is off");
+    const uint32_t k = std::min<uint32_t>(max_tasks, b->n_tasks);
+    IMS_HIP(hipStreamSynchronize((hipStream_t)stream));
+    if (k > 0) {
+        IMS_HIP(hipMemcpy(tasks, b->d_tasks, k * sizeof(uint64_t), hipMemcpyDeviceToHost));
+        IMS_HIP(hipMemcpy(times, b->d_times, 3ull * k * sizeof(uint64_t), hipMemcpyDeviceToHost));
+    }
+    *count = k;
+    return IMS_OK;
+}
+
 int ims_batch_destroy(ims_batch* b)
 {
     if (b) {
@@ -1359,6 +1402,9 @@ int ims_graph_level_directions(ims_graph* g, uint32_t max_levels, uint32_t* dirs
 {
     if (!g || !count || (max_levels > 0 && !dirs)) return fail(IMS_E_INVALID_ARG, "ims_graph_level_directions: bad arguments");
     *count = 0;
+    IMS_HIP(hipStreamSynchronize((hipStream_t)stream));
+    int rc = take_grid_status(g);
+    if (rc) return rc;
     if (g->model != IMS_MODEL_IC || g->last_shape != 2) return IMS_OK;
     const uint32_t k = std::min<uint32_t>(max_levels, std::min<uint32_t>(g->last_steps, g->cap));
     if (k > 0) {

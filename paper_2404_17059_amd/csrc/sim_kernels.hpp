@@ -2290,7 +2290,7 @@ struct SlotBufs {
 // trial part.
 template <typename TaskOf>
 __device__ __forceinline__ void slot_tasks(TaskOf task_of, uint32_t n_tasks, uint32_t* task_counter, const SlotBufs& S,
-                                           uint32_t* status)
+                                           uint32_t* status, uint64_t* times = nullptr)
 {
     __shared__ TaskShared sh;
     const uint64_t slot = blockIdx.x;
@@ -2307,6 +2307,10 @@ __device__ __forceinline__ void slot_tasks(TaskOf task_of, uint32_t n_tasks, uin
         const BatchItem* itp;
         uint32_t w, sp, part;
         task_of(t, itp, w, sp, part);
+        if (times && threadIdx.x == 0) {
+            times[3 * (uint64_t)t] = wall_clock64();
+            times[3 * (uint64_t)t + 2] = slot;
+        }
         const BatchItem& it = *itp;
         const SimParams& P = it.P;
         TaskCtx c;
@@ -2332,6 +2336,7 @@ __device__ __forceinline__ void slot_tasks(TaskOf task_of, uint32_t n_tasks, uin
         const uint32_t steps = lt ? lt_task(P, c, sh, guard) : ic_task(P, c, sh, guard);
         if (threadIdx.x == 0 && lt) S.slot_steps[slot] = c.stamp_base + steps + 1;
         finish_slot_task(c, sh.act, sh, it.total, it.node_counts, it.trial_counts, P.T);
+        if (times && threadIdx.x == 0) times[3 * (uint64_t)t + 1] = wall_clock64();
         max_steps = steps > max_steps ? steps : max_steps;
     }
     if (threadIdx.x == 0) {
@@ -2341,8 +2346,11 @@ __device__ __forceinline__ void slot_tasks(TaskOf task_of, uint32_t n_tasks, uin
     }
 }
 
+// times (or null): per task start and end of the device's constant-rate wall
+// clock and the slot that ran it, [n_tasks][3].
 __global__ __launch_bounds__(kTaskBlock, 4) void batch_kernel(const BatchItem* __restrict__ items, const uint64_t* __restrict__ tasks,
-                                                       uint32_t n_tasks, uint32_t* task_counter, SlotBufs S, uint32_t* status)
+                                                       uint32_t n_tasks, uint32_t* task_counter, SlotBufs S, uint32_t* status,
+                                                       uint64_t* times)
 {
     slot_tasks(
         [&](uint32_t t, const BatchItem*& itp, uint32_t& w, uint32_t& sp, uint32_t& part) {
@@ -2352,7 +2360,7 @@ __global__ __launch_bounds__(kTaskBlock, 4) void batch_kernel(const BatchItem* _
             sp = ((uint32_t)code >> 24) & 7u;
             part = ((uint32_t)code >> 16) & 63u;
         },
-        n_tasks, task_counter, S, status);
+        n_tasks, task_counter, S, status, times);
 }
 
 // Single-run slot form: one item whose words run as 2^sp tasks each (task t =
@@ -2502,6 +2510,21 @@ __global__ __launch_bounds__(kBlock) void reduce_node_counts(const uint64_t* __r
         for (int q = 0; q < kWaves; ++q) s += part[q];
         if (s) atomicAdd(total, s);
     }
+}
+
+// End of a grid-shape run, on the device so the host need not wait for it:
+// status[0] = steps taken (the first step counter that is zero among steps
+// 0 .. next - 1, else next; LT adds the final sweep that changed nothing),
+// status[1] = 1 when the run was cut off at the step guard with work left.
+__global__ void grid_status_kernel(const uint32_t* __restrict__ qcount, uint32_t next, uint32_t cap, uint32_t lt,
+                                   uint32_t* __restrict__ status)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    uint32_t steps = 0;
+    while (steps < next && qcount[steps] != 0) ++steps;
+    status[0] = steps + lt;
+    const uint32_t last = (next + 1 < cap ? next + 1 : cap) - 1;
+    if (next >= cap && qcount[last] != 0) status[1] = 1;
 }
 
 template <typename Tv>
