@@ -459,8 +459,9 @@ class Batch:
 
 def debug_hash(rng_seed: int, domain: int, trials, ids) -> np.ndarray:
     torch = _torch()
-    t = torch.as_tensor(np.ascontiguousarray(trials, dtype=np.int64)).cuda()
-    i = torch.as_tensor(np.ascontiguousarray(ids, dtype=np.int64)).cuda()
+    # uint64 counters pass as their bit patterns
+    t = torch.as_tensor(np.ascontiguousarray(np.asarray(trials).astype(np.uint64)).view(np.int64)).cuda()
+    i = torch.as_tensor(np.ascontiguousarray(np.asarray(ids).astype(np.uint64)).view(np.int64)).cuda()
     out = torch.empty(t.shape[0], dtype=torch.int32, device=t.device)
     _check(_lib.ims_debug_hash(int(rng_seed), int(domain), ctypes.c_void_p(t.data_ptr()),
                                ctypes.c_void_p(i.data_ptr()), ctypes.c_void_p(out.data_ptr()), t.shape[0],

@@ -64,6 +64,69 @@ __device__ __forceinline__ Block4 philox_block(uint64_t c0, uint64_t c1, uint64_
     return Block4{x0, x1, x2, x3};
 }
 
+// The same function with a different instruction schedule, used for the IC
+// arc coins: the middle partial products are summed by one v_mad_u64_u32
+// (mid = xh*ml + xl*mh, whose carry out of bit 64 has weight 2^96) and the
+// columns above bit 32 by a 32-bit carry chain, the first round skips the
+// product of the zero word x2, and each three-way XOR is one v_bitop3_b32 per
+// half.  Both forms give identical words; which one the compiler turns into
+// faster code depends on the call site (measured on MI355X: the IC coin walk
+// of the word-local tasks 1.6x faster with this form, the LT threshold draws
+// 4-16% slower, so each site keeps the faster one).
+__device__ __forceinline__ void mul_wide_chain(uint64_t x, uint64_t m, uint64_t& lo, uint64_t& hi)
+{
+    const uint32_t xl = (uint32_t)x, xh = (uint32_t)(x >> 32);
+    const uint32_t ml = (uint32_t)m, mh = (uint32_t)(m >> 32);
+    const uint64_t p0 = (uint64_t)xl * ml;
+    const uint64_t p1 = (uint64_t)xl * mh;
+    const uint64_t p3 = (uint64_t)xh * mh;
+    const uint64_t mid = (uint64_t)xh * ml + p1;
+    const uint32_t cm = mid < p1 ? 1u : 0u;
+    uint32_t c1, c2, c3;
+    const uint32_t lo_h = __builtin_addc((uint32_t)(p0 >> 32), (uint32_t)mid, 0u, &c1);
+    const uint32_t hi_l = __builtin_addc((uint32_t)p3, (uint32_t)(mid >> 32), c1, &c2);
+    const uint32_t hi_h = __builtin_addc((uint32_t)(p3 >> 32), cm, c2, &c3);
+    lo = ((uint64_t)lo_h << 32) | (uint32_t)p0;
+    hi = ((uint64_t)hi_h << 32) | hi_l;
+}
+
+__device__ __forceinline__ uint64_t xor3_64(uint64_t a, uint64_t b, uint64_t c)
+{
+    const uint32_t l = __builtin_amdgcn_bitop3_b32((uint32_t)a, (uint32_t)b, (uint32_t)c, 0x96);
+    const uint32_t h = __builtin_amdgcn_bitop3_b32((uint32_t)(a >> 32), (uint32_t)(b >> 32), (uint32_t)(c >> 32), 0x96);
+    return (uint64_t)l | ((uint64_t)h << 32);
+}
+
+__device__ __forceinline__ Block4 philox_block_chain(uint64_t c0, uint64_t c1, uint64_t k0, uint64_t k1)
+{
+    uint64_t x0, x1, x2, x3;
+    {
+        uint64_t lo_a, hi_a;
+        mul_wide_chain(c0, kPhiloxM0, lo_a, hi_a);
+        x0 = c1 ^ k0;
+        x1 = 0;
+        x2 = hi_a ^ k1;
+        x3 = lo_a;
+        k0 += kWeyl0;
+        k1 += kWeyl1;
+    }
+#pragma unroll
+    for (int r = 1; r < 10; ++r) {
+        uint64_t lo_a, hi_a, lo_b, hi_b;
+        mul_wide_chain(x0, kPhiloxM0, lo_a, hi_a);
+        mul_wide_chain(x2, kPhiloxM1, lo_b, hi_b);
+        const uint64_t n0 = xor3_64(hi_b, x1, k0);
+        const uint64_t n2 = xor3_64(hi_a, x3, k1);
+        x0 = n0;
+        x1 = lo_b;
+        x2 = n2;
+        x3 = lo_a;
+        k0 += kWeyl0;
+        k1 += kWeyl1;
+    }
+    return Block4{x0, x1, x2, x3};
+}
+
 // The 32-bit value of lane j (0..7) of a block.
 __device__ __forceinline__ uint32_t block_lane(const Block4& b, uint32_t j)
 {
@@ -73,7 +136,9 @@ __device__ __forceinline__ uint32_t block_lane(const Block4& b, uint32_t j)
 
 __device__ __forceinline__ uint32_t hash32(uint64_t rng_seed, uint64_t domain, uint64_t trial, uint64_t id)
 {
-    const Block4 b = philox_block(id, trial >> 3, rng_seed, domain);
+    // the form the simulation uses for this domain
+    const Block4 b = domain == kDomainIcArc ? philox_block_chain(id, trial >> 3, rng_seed, domain)
+                                            : philox_block(id, trial >> 3, rng_seed, domain);
     return block_lane(b, (uint32_t)(trial & 7));
 }
 

@@ -165,7 +165,11 @@ __device__ __forceinline__ uint64_t atomic_or64(uint64_t* p, uint64_t v)
 }
 
 // Live mask of arc e for the trials in `todo` (bits of word w): coins are
-// drawn only for 8-trial groups holding a trial of `todo`.
+// drawn only for 8-trial groups holding a trial of `todo`.  kChain picks the
+// instruction schedule of the hash (same words either way): the carry-chain
+// form everywhere but in the batch kernel, where the plain form measured
+// faster.
+template <bool kChain = true>
 __device__ __forceinline__ uint64_t ic_live(uint64_t todo, uint32_t th, uint64_t e, uint32_t w, uint64_t seed)
 {
     if (th == 0xFFFFFFFFu) return todo;
@@ -173,7 +177,8 @@ __device__ __forceinline__ uint64_t ic_live(uint64_t todo, uint32_t th, uint64_t
     while (rest) {
         const uint32_t g = (uint32_t)__builtin_ctzll(rest) >> 3;
         rest &= ~(0xFFull << (8 * g));
-        const Block4 b = philox_block(e, (uint64_t)w * 8 + g, seed, kDomainIcArc);
+        const Block4 b = kChain ? philox_block_chain(e, (uint64_t)w * 8 + g, seed, kDomainIcArc)
+                                : philox_block(e, (uint64_t)w * 8 + g, seed, kDomainIcArc);
         uint32_t bits = 0;
 #pragma unroll
         for (uint32_t j = 0; j < 8; ++j) bits |= (block_lane(b, j) < th ? 1u : 0u) << j;
@@ -572,6 +577,7 @@ constexpr uint32_t kPullLaneDeg = 32;
 // Pull walk of pair (v, w) by the calling lane alone: eight in-arcs per round,
 // their loads issued together.  Returns the trials that joined; `pend` keeps
 // the ones still pending.
+template <bool kChain = true>
 __device__ __forceinline__ uint64_t ic_pull_lane(const SimParams& P, const uint64_t* __restrict__ Fw, int64_t k0, int64_t k1,
                                                  uint32_t w, uint64_t& pend)
 {
@@ -590,7 +596,7 @@ __device__ __forceinline__ uint64_t ic_pull_lane(const SimParams& P, const uint6
         for (int j = 0; j < 8; ++j) {
             const uint64_t todo = f[j] & pend;
             if (todo == 0) continue;
-            const uint64_t live = ic_live(todo, th[j], sa[j] >> 32, w, P.seed);
+            const uint64_t live = ic_live<kChain>(todo, th[j], sa[j] >> 32, w, P.seed);
             got |= live;
             pend &= ~live;
         }
@@ -602,6 +608,7 @@ __device__ __forceinline__ uint64_t ic_pull_lane(const SimParams& P, const uint6
 // same arguments): 64 in-arcs per round, lane-strided, the joined trials
 // OR-ed over the wavefront after each round so that the walk stops as soon as
 // no trial is pending.
+template <bool kChain = true>
 __device__ __forceinline__ uint64_t ic_pull_wave(const SimParams& P, const uint64_t* __restrict__ Fw, int64_t k0, int64_t k1,
                                                  uint32_t w, uint64_t& pend, uint32_t lane)
 {
@@ -611,7 +618,7 @@ __device__ __forceinline__ uint64_t ic_pull_wave(const SimParams& P, const uint6
         if (k + lane < k1) {
             const uint64_t sa = P.ic_in[k + lane];
             const uint64_t todo = Fw[(uint32_t)sa] & pend;
-            if (todo) mine = ic_live(todo, P.ic_in_thr[k + lane], sa >> 32, w, P.seed);
+            if (todo) mine = ic_live<kChain>(todo, P.ic_in_thr[k + lane], sa >> 32, w, P.seed);
         }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) mine |= __shfl_xor(mine, o);
@@ -1640,6 +1647,7 @@ __device__ __forceinline__ bool hand_over(uint32_t it, uint32_t lane, TaskShared
 // frontier, until every pending trial has joined.  A node is owned by one
 // lane, or by one wavefront when it has more than kPullLaneDeg in-arcs.  New nodes
 // go to the next list with their masks; the caller clears Nw afterwards.
+template <bool kChain = true>
 __device__ __forceinline__ void ic_task_pull_step(const SimParams& P, const TaskCtx& c, TaskShared& sh, uint32_t cur, uint32_t cnt,
                                                   uint64_t vm, bool levels)
 {
@@ -1681,7 +1689,7 @@ __device__ __forceinline__ void ic_task_pull_step(const SimParams& P, const Task
         const bool big = pend != 0 && (uint64_t)(k1 - k0) > kPullLaneDeg;
         if (pend && !big) {
             uint64_t rest = pend;
-            const uint64_t got = ic_pull_lane(P, F, k0, k1, w, rest);
+            const uint64_t got = ic_pull_lane<kChain>(P, F, k0, k1, w, rest);
             if (got) join((uint32_t)v, a, got, rest == 0);
         }
         // nodes with many in-arcs: the wavefront walks them 64 arcs at a time
@@ -1690,7 +1698,7 @@ __device__ __forceinline__ void ic_task_pull_step(const SimParams& P, const Task
             const int j = __builtin_ctzll(bigs);
             bigs &= bigs - 1;
             uint64_t rest = uniform64(__shfl(pend, j));
-            const uint64_t got = ic_pull_wave(P, F, (int64_t)uniform64((uint64_t)__shfl(k0, j)),
+            const uint64_t got = ic_pull_wave<kChain>(P, F, (int64_t)uniform64((uint64_t)__shfl(k0, j)),
                                               (int64_t)uniform64((uint64_t)__shfl(k1, j)), w, rest, lane);
             if (got && lane == (uint32_t)j) join((uint32_t)v, a, got, rest == 0);
         }
@@ -1701,6 +1709,7 @@ __device__ __forceinline__ void ic_task_pull_step(const SimParams& P, const Task
 // and walks their out-arcs lane-strided; a node's first new bit of the step
 // appends it to the next list (counter in LDS); after a barrier the next
 // list picks up its masks from Nw and clears them.  Returns the step count.
+template <bool kChain = true>
 __device__ __forceinline__ uint32_t ic_task(const SimParams& P, const TaskCtx& c, TaskShared& sh, bool& guard)
 {
     const uint32_t lane = threadIdx.x & 63u;
@@ -1782,7 +1791,7 @@ __device__ __forceinline__ uint32_t ic_task(const SimParams& P, const TaskCtx& c
             const uint64_t bw = c.Bw ? c.Bw[v] : 0ull;
             const uint64_t todo = mask & ~(c.Aw[v] | bw);
             if (todo == 0) return;
-            const uint64_t live = ic_live(todo, th, (uint64_t)e, w, P.seed);
+            const uint64_t live = ic_live<kChain>(todo, th, (uint64_t)e, w, P.seed);
             if (live == 0) return;
             const uint64_t old = atomic_or64(&c.Aw[v], live);
             const uint64_t fresh = live & ~old;
@@ -1799,7 +1808,7 @@ __device__ __forceinline__ uint32_t ic_task(const SimParams& P, const TaskCtx& c
             }
         };
         if (pull) {
-            ic_task_pull_step(P, c, sh, cur, cnt, vm, levels);
+            ic_task_pull_step<kChain>(P, c, sh, cur, cnt, vm, levels);
         } else if (narrow) {
             // a lane per frontier node of at most kNarrowDeg out-arcs; the
             // wavefront walks larger ones together
@@ -2288,7 +2297,7 @@ struct SlotBufs {
 // The persistent loop of the slot forms: workgroups take task indices from
 // the counter; task_of(t, item, w, s, part) names the task's item, word and
 // trial part.
-template <typename TaskOf>
+template <bool kChain, typename TaskOf>
 __device__ __forceinline__ void slot_tasks(TaskOf task_of, uint32_t n_tasks, uint32_t* task_counter, const SlotBufs& S,
                                            uint32_t* status, uint64_t* times = nullptr)
 {
@@ -2333,7 +2342,7 @@ __device__ __forceinline__ void slot_tasks(TaskOf task_of, uint32_t n_tasks, uin
         __syncthreads();
         c.stamp_base = sh.base;
         const bool lt = it.model != 0;
-        const uint32_t steps = lt ? lt_task(P, c, sh, guard) : ic_task(P, c, sh, guard);
+        const uint32_t steps = lt ? lt_task(P, c, sh, guard) : ic_task<kChain>(P, c, sh, guard);
         if (threadIdx.x == 0 && lt) S.slot_steps[slot] = c.stamp_base + steps + 1;
         finish_slot_task(c, sh.act, sh, it.total, it.node_counts, it.trial_counts, P.T);
         if (times && threadIdx.x == 0) times[3 * (uint64_t)t + 1] = wall_clock64();
@@ -2352,7 +2361,7 @@ __global__ __launch_bounds__(kTaskBlock, 4) void batch_kernel(const BatchItem* _
                                                        uint32_t n_tasks, uint32_t* task_counter, SlotBufs S, uint32_t* status,
                                                        uint64_t* times)
 {
-    slot_tasks(
+    slot_tasks<false>(
         [&](uint32_t t, const BatchItem*& itp, uint32_t& w, uint32_t& sp, uint32_t& part) {
             const uint64_t code = tasks[t];
             itp = &items[code >> 32];
@@ -2369,7 +2378,7 @@ __global__ __launch_bounds__(kTaskBlock, 4) void batch_kernel(const BatchItem* _
 __global__ __launch_bounds__(kTaskBlock, 4) void slot_run_kernel(const BatchItem* __restrict__ item, uint32_t sp, uint32_t n_tasks,
                                                           uint32_t* task_counter, SlotBufs S, uint32_t* status)
 {
-    slot_tasks(
+    slot_tasks<true>(
         [&](uint32_t t, const BatchItem*& itp, uint32_t& w, uint32_t& spo, uint32_t& part) {
             itp = item;
             w = t >> sp;

@@ -65,9 +65,12 @@ def run_both(ims, model, n, off, idx, param, seeds, T, rs, t_sample=None, opts=N
 def test_device_hash_matches_numpy_philox(ims):
     rng = np.random.default_rng(3)
     trials = rng.integers(0, 10**6, size=300)
-    ids = rng.integers(0, 2**32, size=300)
+    ids = rng.integers(0, 2**32, size=300).astype(np.uint64)
     ids[:8] = 0
     trials[:8] = np.arange(8)
+    # counters above 2^32 (arc ids of graphs with more arcs) and the largest
+    ids[8:16] = rng.integers(2**32, 2**63, size=8).astype(np.uint64)
+    ids[16] = 2**64 - 1
     for dom in (1, 2):
         got = ims.debug_hash(12345, dom, trials, ids)
         exp = [pins.numpy_hash32(12345, dom, int(t), int(i)) for t, i in zip(trials, ids)]
