@@ -142,6 +142,57 @@ def copy_calibration(mib: int) -> int:
     return 0
 
 
+def _counter_sums(dirpath: str):
+    """Per-kernel sums of one rocprofv3 --pmc run's counter (csv output)."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(dirpath, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {dirpath}")
+    per, disp = {}, {}
+    for fn in files:
+        with open(fn) as f:
+            for r in csv.DictReader(f):
+                k = r["Kernel_Name"]
+                per[k] = per.get(k, 0.0) + float(r["Counter_Value"])
+                disp.setdefault(k, set()).add(r.get("Dispatch_Id"))
+    return per, {k: len(v) for k, v in disp.items()}
+
+
+def traffic_record(dirs, copy_mib: int, calls: int, workload: str) -> int:
+    """Measured bytes per call from four rocprofv3 runs (FETCH_SIZE and
+    WRITE_SIZE of the workload, then of the copy calibration): each counter is
+    scaled by the bytes the copy is known to move per KiB it reads, summed over
+    the library's kernels and divided by the calls in the run.  Prints the
+    per-kernel table and writes profiles/traffic_simulate_<workload>.json,
+    keyed to the kernel sources."""
+    fetch, fd = _counter_sums(dirs[0])
+    write, wd = _counter_sums(dirs[1])
+    cfetch, _ = _counter_sums(dirs[2])
+    cwrite, _ = _counter_sums(dirs[3])
+    copy_bytes = 3 * copy_mib * (1 << 20)
+    cf = max(cfetch.values())
+    cw = max(cwrite.values())
+    fscale, wscale = copy_bytes / (cf * 1024), copy_bytes / (cw * 1024)
+    print(f"calibration: the copy reads FETCH_SIZE {cf:.1f} KiB and WRITE_SIZE {cw:.1f} KiB for {copy_bytes} B each way; "
+          f"bytes = FETCH_SIZE x {fscale:.4f} KiB, WRITE_SIZE x {wscale:.4f} KiB")
+    names = sorted(set(fetch) | set(write), key=lambda k: -(fetch.get(k, 0) + write.get(k, 0)))
+    print("| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB |\n|---|---:|---:|---:|")
+    for k in names:
+        print(f"| `{k[:90]}` | {fd.get(k, wd.get(k, 0))} | {fetch.get(k, 0):.0f} | {write.get(k, 0):.0f} |")
+    lib = [k for k in names if "imsim" in k]
+    fb = sum(fetch.get(k, 0) for k in lib) * 1024 * fscale / calls
+    wb = sum(write.get(k, 0) for k in lib) * 1024 * wscale / calls
+    print(f"library kernels per call: read {fb / 1e9:.3f} GB, written {wb / 1e9:.3f} GB, total {(fb + wb) / 1e9:.3f} GB")
+    out = os.path.join(ROOT, "profiles", f"traffic_simulate_{workload}.json")
+    with open(out, "w") as f:
+        json.dump({"workload": workload, "bytes_per_launch": int(fb + wb), "fetch_bytes": int(fb), "write_bytes": int(wb),
+                   "fetch_scale": fscale, "write_scale": wscale, "kernel_source_sha256": kernel_source_sha(),
+                   "source": f"profiles/simulate_{workload}_hbm_traffic.md"}, f, indent=1)
+    print("wrote", out)
+    return 0
+
+
 def run_suite(args) -> int:
     """The nine IC benchmark workloads, each timed as in the main mode; one
     JSON line with the summed work over the summed time and the per-workload
@@ -290,7 +341,14 @@ def main() -> int:
                     help="paper_suite: also run the 1k-node ER and 100k-node BA IC workloads")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB three times (HBM counter calibration)")
+    ap.add_argument("--traffic-record", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="only summarise four rocprofv3 --pmc runs (the workload's FETCH_SIZE and WRITE_SIZE, then the "
+                         "copy calibration's) into profiles/traffic_simulate_<workload>.json")
+    ap.add_argument("--copy-mib", type=int, default=1024, help="--traffic-record: MiB per copy of the calibration run")
+    ap.add_argument("--calls", type=int, default=1, help="--traffic-record: simulate calls in the counted run")
     args = ap.parse_args()
+    if args.traffic_record:
+        return traffic_record(args.traffic_record, args.copy_mib, args.calls, args.workload)
     if args.copy_calibration:
         return copy_calibration(args.copy_calibration)
     if args.gpus != 1:
