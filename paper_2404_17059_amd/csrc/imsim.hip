@@ -106,6 +106,7 @@ struct ims_graph {
     uint64_t* d_lvl = nullptr;       // IC grid shape: per level frontier out-arcs [cap], full-pair in-arcs [cap]
     uint32_t* d_lvl_dir = nullptr;   // IC grid shape: direction of each level [cap]
     uint32_t* d_in_src32 = nullptr;  // source per in-arc (uniform-weight form)
+    uint64_t* d_lt_wout = nullptr;   // LT weight per out-arc (push form of the batch's 8-trial tasks)
     uint32_t* d_node_w = nullptr;    // common weight piece per node (uniform-weight form)
     bool lt_uniform = false;
     uint32_t* d_kinfo = nullptr;     // per node: low half of its in-CSR offset, first plane in the count table
@@ -182,6 +183,7 @@ struct ims_graph {
         dev_free(d_lvl);
         dev_free(d_lvl_dir);
         dev_free(d_in_src32);
+        dev_free(d_lt_wout);
         dev_free(d_node_w);
         dev_free(d_bfirst);
         dev_free(d_bdesc);
@@ -381,6 +383,9 @@ int ims_graph_create(int64_t n, int64_t m, const int64_t* offsets, const uint32_
         const int64_t mi = in_off[n];
         if ((rc = dev_alloc(&g->d_in_off, (uint64_t)n + 1))) return bail(rc);
         if ((rc = dev_alloc(&g->d_in_arc, (uint64_t)mi))) return bail(rc);
+        if ((rc = dev_alloc(&g->d_lt_wout, (uint64_t)m))) return bail(rc);
+        if (m > 0 && hipMemcpy(g->d_lt_wout, param, sizeof(uint64_t) * m, hipMemcpyHostToDevice) != hipSuccess)
+            return bail(fail(IMS_E_HIP, "LT weight upload failed"));
         // equal in-weights form (every node's pieces equal) with its
         // count-threshold planes
         std::vector<uint32_t> node_w, src32;
@@ -1049,7 +1054,8 @@ struct ims_batch {
     uint32_t* d_ctl = nullptr;  // [0] task counter, [1..4] status words (steps, guard, -, refused hand-overs)
     uint64_t* d_times = nullptr;  // per task (start, end, slot) when task timing is on (ims_batch_task_timing)
     bool timing = false;
-    ims_graph::Buf sA, sN, sQ0, sQ1, sQ2, sact, sstamp, ssteps;
+    ims_graph::Buf sA, sN, sQ0, sQ1, sQ2, sact, sstamp, ssteps, srem;
+    bool any_lt = false;
     uint32_t slots = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -1071,7 +1077,7 @@ struct ims_batch {
         dev_free(d_tasks);
         dev_free(d_ctl);
         dev_free(d_times);
-        for (ims_graph::Buf* b : {&sA, &sN, &sQ0, &sQ1, &sQ2, &sact, &sstamp, &ssteps}) ims_graph::release(*b);
+        for (ims_graph::Buf* b : {&sA, &sN, &sQ0, &sQ1, &sQ2, &sact, &sstamp, &ssteps, &srem}) ims_graph::release(*b);
     }
 };
 
@@ -1136,6 +1142,9 @@ int batch_plan(ims_batch* b)
         (rc = batch_buf(b->sQ1, cells * 4)) || (rc = batch_buf(b->sQ2, cells * 16)) || (rc = batch_buf(b->sact, cells * 4)) ||
         (rc = batch_buf(b->sstamp, cells * 4)) || (rc = batch_buf(b->ssteps, (uint64_t)b->slots * 4)))
         return rc;
+    // LT items split into 8-trial tasks run in push form: 8 threshold
+    // remainders per node and slot
+    if (b->any_lt && b->tuning.split >= 8 && (rc = batch_buf(b->srem, cells * 64))) return rc;
     b->drop_graph();
     return IMS_OK;
 }
@@ -1163,7 +1172,8 @@ int batch_enqueue(ims_batch* b, hipStream_t s)
                       (uint64_t*)b->sQ2.p,
                       (uint32_t*)b->sact.p,
                       (uint32_t*)b->sstamp.p,
-                      (uint32_t*)b->ssteps.p};
+                      (uint32_t*)b->ssteps.p,
+                      b->tuning.split >= 8 ? (uint64_t*)b->srem.p : nullptr};
     hipLaunchKernelGGL(imsim::batch_kernel, dim3(b->slots), dim3(imsim::kTaskBlock), 0, s, (const imsim::BatchItem*)b->d_items,
                        (const uint64_t*)b->d_tasks, b->n_tasks, b->d_ctl, S, b->d_ctl + 1, b->timing ? b->d_times : nullptr);
     IMS_HIP(hipGetLastError());
@@ -1222,11 +1232,13 @@ int ims_batch_create(const ims_batch_item* items, uint32_t n_items, const ims_tu
         P.in_src32 = g->d_in_src32;
         P.node_w = g->d_node_w;
         P.lt_uniform = g->lt_uniform ? 1 : 0;
+        P.lt_wout = g->d_lt_wout;
         if ((rc = set_ic_direction(P, g, b->tuning.ic_alpha, b->tuning.ic_beta, 0))) return bail(rc);
         P.seeds = d;
         P.n_seeds = (uint32_t)sv.size();
         P.cap = g->cap;
         bi.model = g->model;
+        if (g->model == IMS_MODEL_LT) b->any_lt = true;
         bi.trial_counts = it.trial_counts;
         bi.node_counts = it.node_counts;
         bi.total = it.total;

@@ -70,6 +70,9 @@ struct SimParams {
     const uint32_t* __restrict__ in_src32;
     const uint32_t* __restrict__ node_w;
     int lt_uniform;
+    // LT: weight of every out-arc (out-CSR order) in 2^-32 units, for the
+    // push form of the 8-trial batch tasks
+    const uint64_t* __restrict__ lt_wout;
     // LT grid shape: top 16 bits of every threshold hash, [W][n][64] (or null)
     const uint16_t* __restrict__ thp;
     uint32_t thp_shift;  // the table holds hash >> thp_shift (16, or 31 in tests)
@@ -197,6 +200,12 @@ struct ArcStage {
 __device__ __forceinline__ uint32_t uniform32(uint32_t x)
 {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
+}
+
+// x of lane j (j may differ between lanes), as two 32-bit shuffles
+__device__ __forceinline__ uint64_t shfl64(uint64_t x, uint32_t j)
+{
+    return (uint64_t)(uint32_t)__shfl((int)(uint32_t)x, (int)j) | ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(x >> 32), (int)j) << 32);
 }
 
 __device__ __forceinline__ uint64_t uniform64(uint64_t x)
@@ -1594,6 +1603,7 @@ struct TaskCtx {
     uint32_t* stamp;       // LT: last stamp that collected each node
     uint32_t stamp_base;   // LT: stamps of this task are stamp_base + step
     uint32_t* act;         // slot forms: activated nodes (else null)
+    uint64_t* rem;         // batch slots, LT push form: 8 threshold remainders per node (else null)
     const uint32_t* seeds;
     uint32_t n_seeds;
 };
@@ -1949,11 +1959,159 @@ __device__ __forceinline__ uint64_t lt_eval_lane(const SimParams& P, const uint6
     return (uint64_t)d8 << sh;
 }
 
+// LT cascade of one 8-trial task in push form (the batch's narrow tasks
+// without level counts).  Section 2's rule, v joins when the weight of its
+// active in-neighbours exceeds its threshold h, is kept as a remainder
+// r = h - (weight of the in-neighbours active so far) per (node, trial):
+// a node that joins subtracts its out-arcs' weights from their targets'
+// remainders in the next step, and a target joins in a trial when a
+// subtraction takes its remainder below zero.  Each remainder is one 64-bit
+// word, task tag (31 bits) | joined (1 bit) | remainder (32 bits), updated by
+// compare-and-swap; a word that carries another task's tag holds nothing yet
+// and starts from h = H(seed, LT, t, v), drawn then, so the words need no
+// clearing between tasks.  Where the pull form reads every in-arc of every
+// candidate once per step, this form touches one word per out-arc and newly
+// joined trial.  Joins in a step become visible within it, but the fixpoint
+// (the final state) is the same.  The wavefront spreads the out-arcs of 64
+// frontier nodes over its lanes (a prefix sum of their degrees and a binary
+// search for each arc's node), so hubs and small nodes mix.
+__device__ __forceinline__ uint32_t lt_task_push(const SimParams& P, const TaskCtx& c, TaskShared& sh, bool& guard)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t w = c.w;
+    const uint32_t g = c.group;
+    const uint32_t s8 = 8 * g;
+    const uint64_t vm = valid_mask(w, P.W, P.T) & c.tmask;
+    const uint64_t tag = (uint64_t)((c.stamp_base + 1u) & 0x7FFFFFFFu) << 33;
+    constexpr uint64_t kJoined = 1ull << 32;
+    uint64_t* Nn = c.Nw;  // trials that joined and are not pushed yet (zero between tasks)
+    if (threadIdx.x == 0) {
+        sh.cnt[0] = 0;
+        sh.cnt[1] = 0;
+        sh.act = 0;
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < c.n_seeds; i += kTaskBlock) {
+        const uint32_t sd = c.seeds[i];
+        const uint64_t nb = vm & ~(c.Bw ? c.Bw[sd] : 0ull);
+        if (nb == 0) continue;
+        c.Aw[sd] = nb;
+        Nn[sd] = nb;
+        c.L[0][atomicAdd(&sh.cnt[0], 1u)] = sd;
+        if (c.act) c.act[atomicAdd(&sh.act, 1u)] = sd;
+    }
+    __syncthreads();
+    uint32_t cur = 0, steps = 0;
+    for (;;) {
+        const uint32_t cnt = sh.cnt[cur];
+        if (cnt == 0) break;
+        const uint32_t* Lc = cur ? c.L[1] : c.L[0];
+        if (steps + 1 >= P.cap) {
+            guard = true;
+            for (uint32_t i = threadIdx.x; i < cnt; i += kTaskBlock) Nn[Lc[i]] = 0;
+            break;
+        }
+        ++steps;
+        const uint32_t nxt = cur ^ 1u;
+        uint32_t* Ln = nxt ? c.L[1] : c.L[0];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            sh.cnt[nxt] = 0;
+            sh.next_item = 0;
+        }
+        __syncthreads();
+        for (;;) {
+            uint32_t it = 0;
+            if (lane == 0) it = atomicAdd(&sh.next_item, 64u);
+            it = __shfl(it, 0);
+            if (it >= cnt) break;
+            const uint32_t u = it + lane < cnt ? Lc[it + lane] : 0u;
+            const uint64_t m = it + lane < cnt ? atomicExch((unsigned long long*)&Nn[u], 0ull) & vm : 0ull;
+            const int64_t e0 = m ? P.off[u] : 0;
+            const uint32_t deg = m ? (uint32_t)(P.off[u + 1] - e0) : 0u;
+            uint32_t incl = deg;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t y = __shfl_up(incl, o);
+                incl += lane >= (uint32_t)o ? y : 0u;
+            }
+            const uint32_t total = uniform32(__shfl(incl, 63));
+            for (uint32_t base = 0; base < total; base += 64) {
+                const uint32_t q = base + lane;
+                // the arc's node: the number of lanes whose inclusive degree
+                // sum is at most q
+                uint32_t j = 0;
+#pragma unroll
+                for (uint32_t stp = 32; stp > 0; stp >>= 1) {
+                    const uint32_t im = (uint32_t)__shfl((int)incl, (int)(j + stp - 1));
+                    j += im <= q ? stp : 0u;
+                }
+                const uint32_t jc = j < 64u ? j : 63u;
+                const uint32_t inc_j = (uint32_t)__shfl((int)incl, (int)jc);
+                const uint32_t deg_j = (uint32_t)__shfl((int)deg, (int)jc);
+                const int64_t e0_j = (int64_t)shfl64((uint64_t)e0, jc);
+                const uint64_t m_j = shfl64(m, jc);
+                if (q >= total) continue;
+                const int64_t e = e0_j + (int64_t)(q - (inc_j - deg_j));
+                const uint32_t v = P.idx[e];
+                const uint64_t wt = P.lt_wout[e];
+                if (wt == 0) continue;
+                const uint64_t av = load_relaxed(&c.Aw[v]) | (c.Bw ? c.Bw[v] : 0ull);
+                uint64_t todo = m_j & ~av;
+                if (todo == 0) continue;
+                uint64_t* r = c.rem + (uint64_t)v * 8;
+                uint64_t dec = 0;
+                bool drawn = false;
+                Block4 blk{0, 0, 0, 0};
+                while (todo) {
+                    const uint32_t b = (uint32_t)__builtin_ctzll(todo);
+                    todo &= todo - 1;
+                    const uint32_t k = (b - s8) & 7u;
+                    uint64_t old = load_relaxed(&r[k]);
+                    for (;;) {
+                        uint64_t rem;
+                        if ((old >> 33) != (tag >> 33)) {
+                            if (!drawn) {
+                                blk = philox_block(v, (uint64_t)w * 8 + g, P.seed, kDomainLtNode);
+                                drawn = true;
+                            }
+                            rem = block_lane(blk, k);
+                        } else {
+                            if (old & kJoined) break;  // this trial joined already
+                            rem = (uint32_t)old;
+                        }
+                        const bool cross = wt > rem;
+                        const uint64_t nw = tag | (cross ? kJoined : rem - wt);
+                        const uint64_t prev = atomicCAS((unsigned long long*)&r[k], (unsigned long long)old, (unsigned long long)nw);
+                        if (prev == old) {
+                            if (cross) dec |= 1ull << b;
+                            break;
+                        }
+                        old = prev;
+                    }
+                }
+                if (dec) {
+                    const uint64_t oa = atomic_or64(&c.Aw[v], dec);
+                    const uint64_t fresh = dec & ~oa;
+                    if (fresh) {
+                        if (atomic_or64(&Nn[v], fresh) == 0) Ln[atomicAdd(&sh.cnt[nxt], 1u)] = v;
+                        if (c.act && oa == 0) c.act[atomicAdd(&sh.act, 1u)] = v;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        cur = nxt;
+    }
+    return steps;
+}
+
 // LT cascade of one task.  The frontier list holds the nodes that joined in
 // the previous step (any trial); their out-neighbours with an inactive trial
 // are collected once each into a candidate list (stamp_base + step marks the
 // collection), then wavefronts evaluate candidates eight at a time; nodes
 // that joined form the next frontier.  Returns the step count.
+template <bool kPush = false>
 __device__ __forceinline__ uint32_t lt_task(const SimParams& P, const TaskCtx& c, TaskShared& sh, bool& guard)
 {
     const uint32_t lane = threadIdx.x & 63u;
@@ -1964,6 +2122,9 @@ __device__ __forceinline__ uint32_t lt_task(const SimParams& P, const TaskCtx& c
     // sees the state the step started from, and the joins (held in Nw) land
     // at the step's end, so step l activates exactly the nodes of level l
     const bool levels = P.level_counts != nullptr;
+    if constexpr (kPush) {
+        if (narrow && !levels && c.rem && P.lt_wout) return lt_task_push(P, c, sh, guard);
+    }
     if (threadIdx.x == 0) {
         sh.cnt[0] = 0;
         sh.cnt[1] = 0;
@@ -2202,6 +2363,7 @@ __global__ __launch_bounds__(kTaskBlock, 2) void word_kernel(SimParams P, uint64
         const uint32_t t = sh.task;
         if (t >= n_tasks) break;
         TaskCtx c;
+        c.rem = nullptr;
         c.tmask = ~0ull;
         c.group = 8;
         uint32_t set = 0;
@@ -2292,12 +2454,13 @@ struct SlotBufs {
     uint32_t* sact;
     uint32_t* sstamp;
     uint32_t* slot_steps;
+    uint64_t* srem;  // [slot][max_n][8] LT threshold remainders (the batch form), else null
 };
 
 // The persistent loop of the slot forms: workgroups take task indices from
 // the counter; task_of(t, item, w, s, part) names the task's item, word and
 // trial part.
-template <bool kChain, typename TaskOf>
+template <bool kChain, bool kPush, typename TaskOf>
 __device__ __forceinline__ void slot_tasks(TaskOf task_of, uint32_t n_tasks, uint32_t* task_counter, const SlotBufs& S,
                                            uint32_t* status, uint64_t* times = nullptr)
 {
@@ -2338,11 +2501,12 @@ __device__ __forceinline__ void slot_tasks(TaskOf task_of, uint32_t n_tasks, uin
         c.M[1] = c.M[0] + max_n;
         c.C = (uint32_t*)(S.sQ2 + slot * max_n * 2);
         c.stamp = S.sstamp + slot * max_n;
+        c.rem = S.srem ? S.srem + slot * max_n * 8 : nullptr;
         if (threadIdx.x == 0) sh.base = S.slot_steps[slot];
         __syncthreads();
         c.stamp_base = sh.base;
         const bool lt = it.model != 0;
-        const uint32_t steps = lt ? lt_task(P, c, sh, guard) : ic_task<kChain>(P, c, sh, guard);
+        const uint32_t steps = lt ? lt_task<kPush>(P, c, sh, guard) : ic_task<kChain>(P, c, sh, guard);
         if (threadIdx.x == 0 && lt) S.slot_steps[slot] = c.stamp_base + steps + 1;
         finish_slot_task(c, sh.act, sh, it.total, it.node_counts, it.trial_counts, P.T);
         if (times && threadIdx.x == 0) times[3 * (uint64_t)t + 1] = wall_clock64();
@@ -2361,7 +2525,7 @@ __global__ __launch_bounds__(kTaskBlock, 4) void batch_kernel(const BatchItem* _
                                                        uint32_t n_tasks, uint32_t* task_counter, SlotBufs S, uint32_t* status,
                                                        uint64_t* times)
 {
-    slot_tasks<false>(
+    slot_tasks<false, true>(
         [&](uint32_t t, const BatchItem*& itp, uint32_t& w, uint32_t& sp, uint32_t& part) {
             const uint64_t code = tasks[t];
             itp = &items[code >> 32];
@@ -2378,7 +2542,7 @@ __global__ __launch_bounds__(kTaskBlock, 4) void batch_kernel(const BatchItem* _
 __global__ __launch_bounds__(kTaskBlock, 4) void slot_run_kernel(const BatchItem* __restrict__ item, uint32_t sp, uint32_t n_tasks,
                                                           uint32_t* task_counter, SlotBufs S, uint32_t* status)
 {
-    slot_tasks<true>(
+    slot_tasks<true, false>(
         [&](uint32_t t, const BatchItem*& itp, uint32_t& w, uint32_t& spo, uint32_t& part) {
             itp = item;
             w = t >> sp;
