@@ -1997,6 +1997,8 @@ __device__ __forceinline__ uint32_t lt_task_push(const SimParams& P, const TaskC
         if (nb == 0) continue;
         c.Aw[sd] = nb;
         Nn[sd] = nb;
+        // a seed's trials count as joined: its remainders never cross
+        for (uint64_t bm = nb; bm; bm &= bm - 1) c.rem[(uint64_t)sd * 8 + ((__builtin_ctzll(bm) - s8) & 7u)] = tag | kJoined;
         c.L[0][atomicAdd(&sh.cnt[0], 1u)] = sd;
         if (c.act) c.act[atomicAdd(&sh.act, 1u)] = sd;
     }
@@ -2056,9 +2058,9 @@ __device__ __forceinline__ uint32_t lt_task_push(const SimParams& P, const TaskC
                 const uint32_t v = P.idx[e];
                 const uint64_t wt = P.lt_wout[e];
                 if (wt == 0) continue;
-                const uint64_t av = load_relaxed(&c.Aw[v]) | (c.Bw ? c.Bw[v] : 0ull);
-                uint64_t todo = m_j & ~av;
-                if (todo == 0) continue;
+                // trials where v is active already carry the joined bit (seeds
+                // from the start, the others from their crossing)
+                uint64_t todo = m_j;
                 uint64_t* r = c.rem + (uint64_t)v * 8;
                 uint64_t dec = 0;
                 bool drawn = false;
@@ -2091,12 +2093,11 @@ __device__ __forceinline__ uint32_t lt_task_push(const SimParams& P, const TaskC
                     }
                 }
                 if (dec) {
+                    // each (node, trial) crosses once, so dec holds new trials only
                     const uint64_t oa = atomic_or64(&c.Aw[v], dec);
-                    const uint64_t fresh = dec & ~oa;
-                    if (fresh) {
-                        if (atomic_or64(&Nn[v], fresh) == 0) Ln[atomicAdd(&sh.cnt[nxt], 1u)] = v;
-                        if (c.act && oa == 0) c.act[atomicAdd(&sh.act, 1u)] = v;
-                    }
+                    const uint64_t on = atomic_or64(&Nn[v], dec);
+                    if (on == 0) Ln[atomicAdd(&sh.cnt[nxt], 1u)] = v;
+                    if (c.act && oa == 0) c.act[atomicAdd(&sh.act, 1u)] = v;
                 }
             }
         }
@@ -2123,7 +2124,7 @@ __device__ __forceinline__ uint32_t lt_task(const SimParams& P, const TaskCtx& c
     // at the step's end, so step l activates exactly the nodes of level l
     const bool levels = P.level_counts != nullptr;
     if constexpr (kPush) {
-        if (narrow && !levels && c.rem && P.lt_wout) return lt_task_push(P, c, sh, guard);
+        if (narrow && !levels && c.rem && !c.Bw && P.lt_wout) return lt_task_push(P, c, sh, guard);
     }
     if (threadIdx.x == 0) {
         sh.cnt[0] = 0;
@@ -2328,7 +2329,9 @@ __device__ __forceinline__ void finish_slot_task(const TaskCtx& c, uint32_t n_ac
             c.Aw[v] = 0;
         }
         if (trial_counts) {
-            for (uint32_t b = 0; b < 64; ++b) {
+            // only the task's trials can be set
+            for (uint64_t bm = c.tmask; bm; bm &= bm - 1) {
+                const uint32_t b = (uint32_t)__builtin_ctzll(bm);
                 const uint64_t bal = __ballot((x >> b) & 1ull);
                 tcount += (lane == b) ? (uint32_t)__popcll(bal) : 0u;
             }
