@@ -559,6 +559,61 @@ def test_batch_split_tasks_equal_single_runs(ims, split):
         it[0].close()
 
 
+def test_batch_lt_push_form_edge_weights(ims):
+    """The push form of the 8-trial LT tasks (threshold remainders) on LT
+    weights that reach its edge cases: an arc of weight exactly 1 (its
+    target's only in-weight: it always joins), arcs of weight 0 (never
+    counted), in-weights summing to exactly 1, a node whose in-weights are
+    one tiny and one large arc, seeds that point at each other and at
+    already-active nodes, a hub with more out-arcs than a wavefront; every
+    item equals the oracle over all trials, on launches with 8, then 1, then
+    8 trials per task again (remainder words written by earlier tasks on the
+    same slots must not leak into later ones)."""
+    import torch
+    rng = np.random.default_rng(41)
+    items, specs = [], []
+    # 1: a path with weight-1 arcs and a cycle back (every node joins)
+    n = 300
+    src = np.arange(n - 1); dst = src + 1
+    g = synth.from_arcs(n, np.concatenate([src, [n - 1]]), np.concatenate([dst, [0]]))
+    specs.append((g, np.ones(g.m), [0], 200, 11))
+    # 2: ER with a third of the arcs at weight 0 and the rest summing to 1
+    g = synth.erdos_renyi_directed(800, 5.0, 42)
+    u = rng.uniform(0.0, 1.0, size=g.m)
+    u[rng.random(g.m) < 0.33] = 0.0
+    insum = np.bincount(g.indices, weights=u, minlength=g.n)
+    w = np.where(insum[g.indices] > 0, u / np.maximum(insum[g.indices], 1e-300), 0.0)
+    specs.append((g, w, synth.random_seeds(g.n, 6, 43), 190, 12))
+    # 3: a star hub (out-degree 700) into nodes with one tiny and one large in-arc
+    n = 1500
+    hub_src = np.zeros(700, dtype=np.int64); hub_dst = np.arange(1, 701)
+    side_src = np.arange(701, 1401); side_dst = np.arange(1, 701)
+    g = synth.from_arcs(n, np.concatenate([hub_src, side_src]), np.concatenate([hub_dst, side_dst]))
+    wt = np.where(np.repeat(np.arange(g.n), np.diff(g.offsets)) == 0, 1e-9, 0.999)
+    specs.append((g, wt, [0, 701, 702, 5], 64, 13))
+    # 4: BA graph, 1/indeg weights, seeds adjacent to each other
+    g = synth.barabasi_albert(2000, 3, 44)
+    sd = [int(x) for x in g.indices[g.offsets[0]:g.offsets[0] + 5]] + [0]
+    specs.append((g, synth.weighted_cascade(g), sd, 100, 14))
+    for g, w, sd, T, rs in specs:
+        items.append((ims.Graph(g.n, g.offsets, g.indices, "lt", w), np.asarray(sd, dtype=np.int64), T, rs))
+    refs = [oracle.simulate("lt", g.n, g.offsets, g.indices, oracle.encode("lt", w), np.unique(np.asarray(sd)), T, rs)
+            for g, w, sd, T, rs in specs]
+    for split in (8, 1, 8):
+        B = ims.Batch(items, tuning=(2, 0, split))
+        for rep in range(2):
+            say(f"[parity] LT push-form edge weights, split {split}, replay {rep}")
+            B.launch()
+            torch.cuda.synchronize()
+            for k, (r, ref) in enumerate(zip(B.results(), refs)):
+                assert r["total"] == ref["total"], (split, rep, k)
+                assert (r["trial_counts"] == ref["trial_counts"]).all(), (split, rep, k)
+                assert (r["node_counts"] == ref["node_counts"]).all(), (split, rep, k)
+        B.close()
+    for it in items:
+        it[0].close()
+
+
 def test_batch_64_items_full(ims):
     """The 64-item uneven batch (ER / BA, IC-WC / LT-1/indeg, n 1k-200k, 2,000
     trials each) in one persistent launch with the default schedule: every
