@@ -248,7 +248,7 @@ typedef struct ims_tuning {
     double ic_beta;         /* IC tasks' pull -> push switch point (ims_opts.ic_beta), 0 = 24 */
 } ims_tuning;
 
-/* tuning NULL = defaults (2 per CU, largest first, 8 tasks per word, default
+/* tuning NULL = defaults (2 per CU, largest first, 4 tasks per word, default
  * switch points).  Synchronous. */
 int ims_batch_create(const ims_batch_item* items, uint32_t n_items, const ims_tuning* tuning, ims_batch** out);
 /* Time candidate schedules `repeats` times each on `stream`: first

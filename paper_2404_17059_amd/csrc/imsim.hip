@@ -1045,7 +1045,7 @@ struct ims_batch {
     std::vector<imsim::BatchItem> host_items;
     std::vector<uint32_t*> dev_seeds;
     std::vector<double> cost;
-    ims_tuning tuning{2, 0, 8, 0.0, 0.0};
+    ims_tuning tuning{2, 0, 4, 0.0, 0.0};
     int device = 0, cus = 0;
     uint64_t max_n = 1;
     uint32_t n_tasks = 0;
@@ -1142,9 +1142,9 @@ int batch_plan(ims_batch* b)
         (rc = batch_buf(b->sQ1, cells * 4)) || (rc = batch_buf(b->sQ2, cells * 16)) || (rc = batch_buf(b->sact, cells * 4)) ||
         (rc = batch_buf(b->sstamp, cells * 4)) || (rc = batch_buf(b->ssteps, (uint64_t)b->slots * 4)))
         return rc;
-    // LT items split into 8-trial tasks run in push form: 8 threshold
-    // remainders per node and slot
-    if (b->any_lt && b->tuning.split >= 8 && (rc = batch_buf(b->srem, cells * 64))) return rc;
+    // LT items split into tasks of at most 16 trials run in push form: 16
+    // threshold remainders per node and slot
+    if (b->any_lt && b->tuning.split >= 4 && (rc = batch_buf(b->srem, cells * 8 * imsim::kRemWords))) return rc;
     b->drop_graph();
     return IMS_OK;
 }
@@ -1173,7 +1173,7 @@ int batch_enqueue(ims_batch* b, hipStream_t s)
                       (uint32_t*)b->sact.p,
                       (uint32_t*)b->sstamp.p,
                       (uint32_t*)b->ssteps.p,
-                      b->tuning.split >= 8 ? (uint64_t*)b->srem.p : nullptr};
+                      b->tuning.split >= 4 ? (uint64_t*)b->srem.p : nullptr};
     hipLaunchKernelGGL(imsim::batch_kernel, dim3(b->slots), dim3(imsim::kTaskBlock), 0, s, (const imsim::BatchItem*)b->d_items,
                        (const uint64_t*)b->d_tasks, b->n_tasks, b->d_ctl, S, b->d_ctl + 1, b->timing ? b->d_times : nullptr);
     IMS_HIP(hipGetLastError());
@@ -1332,8 +1332,8 @@ int ims_batch_autotune(ims_batch* b, int repeats, void* stream, ims_tuning* chos
         return IMS_OK;
     };
     // stage 1: launch shape and task size at the default switch points
-    const ims_tuning shapes[] = {{2, 0, 1, 0, 0}, {2, 0, 4, 0, 0}, {2, 0, 8, 0, 0}, {4, 0, 8, 0, 0},
-                                 {2, 1, 8, 0, 0}, {2, 0, 16, 0, 0}, {2, 0, 64, 0, 0}};
+    const ims_tuning shapes[] = {{2, 0, 2, 0, 0}, {2, 0, 4, 0, 0}, {4, 0, 4, 0, 0}, {2, 1, 4, 0, 0},
+                                 {2, 0, 8, 0, 0}, {4, 0, 8, 0, 0}, {2, 0, 16, 0, 0}};
     for (const ims_tuning& c : shapes)
         if ((rc = trial(c))) break;
     // stage 2: IC switch points for the best shape (1e-9: push only)

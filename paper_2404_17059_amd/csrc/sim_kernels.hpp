@@ -1590,6 +1590,8 @@ struct TaskShared {
 };
 
 // Where one task keeps its state.
+constexpr uint32_t kRemWords = 16;  // LT push form: remainder words per node and slot (tasks of at most 16 trials)
+
 struct TaskCtx {
     uint32_t w;
     uint64_t tmask;        // the task's trials within word w (all 64 but in split batch tasks)
@@ -1603,7 +1605,8 @@ struct TaskCtx {
     uint32_t* stamp;       // LT: last stamp that collected each node
     uint32_t stamp_base;   // LT: stamps of this task are stamp_base + step
     uint32_t* act;         // slot forms: activated nodes (else null)
-    uint64_t* rem;         // batch slots, LT push form: 8 threshold remainders per node (else null)
+    uint64_t* rem;         // batch slots, LT push form: threshold remainders, rem_stride per node (else null)
+    uint32_t rem_stride;   // the task's trials when at most kRemWords (else 0)
     const uint32_t* seeds;
     uint32_t n_seeds;
 };
@@ -1959,8 +1962,8 @@ __device__ __forceinline__ uint64_t lt_eval_lane(const SimParams& P, const uint6
     return (uint64_t)d8 << sh;
 }
 
-// LT cascade of one 8-trial task in push form (the batch's narrow tasks
-// without level counts).  Section 2's rule, v joins when the weight of its
+// LT cascade of one task of at most 16 trials in push form (the batch's
+// tasks of 8 or 16 trials, without level counts).  Section 2's rule, v joins when the weight of its
 // active in-neighbours exceeds its threshold h, is kept as a remainder
 // r = h - (weight of the in-neighbours active so far) per (node, trial):
 // a node that joins subtracts its out-arcs' weights from their targets'
@@ -1974,13 +1977,15 @@ __device__ __forceinline__ uint64_t lt_eval_lane(const SimParams& P, const uint6
 // joined trial.  Joins in a step become visible within it, but the fixpoint
 // (the final state) is the same.  The wavefront spreads the out-arcs of 64
 // frontier nodes over its lanes (a prefix sum of their degrees and a binary
-// search for each arc's node), so hubs and small nodes mix.
+// search for each arc's node), so hubs and small nodes mix.  A node keeps
+// one remainder word per trial of the task (c.rem_stride of them: the task's
+// trials are consecutive bits of word w, from bit t0), at most kRemWords.
+
 __device__ __forceinline__ uint32_t lt_task_push(const SimParams& P, const TaskCtx& c, TaskShared& sh, bool& guard)
 {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t w = c.w;
-    const uint32_t g = c.group;
-    const uint32_t s8 = 8 * g;
+    const uint32_t t0 = (uint32_t)__builtin_ctzll(c.tmask);
     const uint64_t vm = valid_mask(w, P.W, P.T) & c.tmask;
     const uint64_t tag = (uint64_t)((c.stamp_base + 1u) & 0x7FFFFFFFu) << 33;
     constexpr uint64_t kJoined = 1ull << 32;
@@ -1998,7 +2003,7 @@ __device__ __forceinline__ uint32_t lt_task_push(const SimParams& P, const TaskC
         c.Aw[sd] = nb;
         Nn[sd] = nb;
         // a seed's trials count as joined: its remainders never cross
-        for (uint64_t bm = nb; bm; bm &= bm - 1) c.rem[(uint64_t)sd * 8 + ((__builtin_ctzll(bm) - s8) & 7u)] = tag | kJoined;
+        for (uint64_t bm = nb; bm; bm &= bm - 1) c.rem[(uint64_t)sd * c.rem_stride + (__builtin_ctzll(bm) - t0)] = tag | kJoined;
         c.L[0][atomicAdd(&sh.cnt[0], 1u)] = sd;
         if (c.act) c.act[atomicAdd(&sh.act, 1u)] = sd;
     }
@@ -2061,23 +2066,23 @@ __device__ __forceinline__ uint32_t lt_task_push(const SimParams& P, const TaskC
                 // trials where v is active already carry the joined bit (seeds
                 // from the start, the others from their crossing)
                 uint64_t todo = m_j;
-                uint64_t* r = c.rem + (uint64_t)v * 8;
+                uint64_t* r = c.rem + (uint64_t)v * c.rem_stride;
                 uint64_t dec = 0;
-                bool drawn = false;
+                uint32_t drawn = 8;  // the 8-trial group whose block blk holds (8: none)
                 Block4 blk{0, 0, 0, 0};
                 while (todo) {
                     const uint32_t b = (uint32_t)__builtin_ctzll(todo);
                     todo &= todo - 1;
-                    const uint32_t k = (b - s8) & 7u;
+                    const uint32_t k = b - t0;
                     uint64_t old = load_relaxed(&r[k]);
                     for (;;) {
                         uint64_t rem;
                         if ((old >> 33) != (tag >> 33)) {
-                            if (!drawn) {
-                                blk = philox_block(v, (uint64_t)w * 8 + g, P.seed, kDomainLtNode);
-                                drawn = true;
+                            if (drawn != (b >> 3)) {
+                                drawn = b >> 3;
+                                blk = philox_block(v, (uint64_t)w * 8 + drawn, P.seed, kDomainLtNode);
                             }
-                            rem = block_lane(blk, k);
+                            rem = block_lane(blk, b & 7u);
                         } else {
                             if (old & kJoined) break;  // this trial joined already
                             rem = (uint32_t)old;
@@ -2124,7 +2129,7 @@ __device__ __forceinline__ uint32_t lt_task(const SimParams& P, const TaskCtx& c
     // at the step's end, so step l activates exactly the nodes of level l
     const bool levels = P.level_counts != nullptr;
     if constexpr (kPush) {
-        if (narrow && !levels && c.rem && !c.Bw && P.lt_wout) return lt_task_push(P, c, sh, guard);
+        if (!levels && c.rem && c.rem_stride && !c.Bw && P.lt_wout) return lt_task_push(P, c, sh, guard);
     }
     if (threadIdx.x == 0) {
         sh.cnt[0] = 0;
@@ -2367,6 +2372,7 @@ __global__ __launch_bounds__(kTaskBlock, 2) void word_kernel(SimParams P, uint64
         if (t >= n_tasks) break;
         TaskCtx c;
         c.rem = nullptr;
+        c.rem_stride = 0;
         c.tmask = ~0ull;
         c.group = 8;
         uint32_t set = 0;
@@ -2457,7 +2463,7 @@ struct SlotBufs {
     uint32_t* sact;
     uint32_t* sstamp;
     uint32_t* slot_steps;
-    uint64_t* srem;  // [slot][max_n][8] LT threshold remainders (the batch form), else null
+    uint64_t* srem;  // [slot][max_n][kRemWords] LT threshold remainders (the batch form), else null
 };
 
 // The persistent loop of the slot forms: workgroups take task indices from
@@ -2504,7 +2510,8 @@ __device__ __forceinline__ void slot_tasks(TaskOf task_of, uint32_t n_tasks, uin
         c.M[1] = c.M[0] + max_n;
         c.C = (uint32_t*)(S.sQ2 + slot * max_n * 2);
         c.stamp = S.sstamp + slot * max_n;
-        c.rem = S.srem ? S.srem + slot * max_n * 8 : nullptr;
+        c.rem = S.srem ? S.srem + slot * max_n * kRemWords : nullptr;
+        c.rem_stride = (64u >> sp) <= kRemWords ? 64u >> sp : 0u;
         if (threadIdx.x == 0) sh.base = S.slot_steps[slot];
         __syncthreads();
         c.stamp_base = sh.base;

@@ -566,9 +566,10 @@ def test_batch_lt_push_form_edge_weights(ims):
     counted), in-weights summing to exactly 1, a node whose in-weights are
     one tiny and one large arc, seeds that point at each other and at
     already-active nodes, a hub with more out-arcs than a wavefront; every
-    item equals the oracle over all trials, on launches with 8, then 1, then
-    8 trials per task again (remainder words written by earlier tasks on the
-    same slots must not leak into later ones)."""
+    item equals the oracle over all trials, on launches with 8, then 64, then
+    16, then 8 trials per task again (push, pull, push over two 8-trial
+    groups, push: remainder words written by earlier tasks on the same slots
+    must not leak into later ones)."""
     import torch
     rng = np.random.default_rng(41)
     items, specs = [], []
@@ -599,7 +600,7 @@ def test_batch_lt_push_form_edge_weights(ims):
         items.append((ims.Graph(g.n, g.offsets, g.indices, "lt", w), np.asarray(sd, dtype=np.int64), T, rs))
     refs = [oracle.simulate("lt", g.n, g.offsets, g.indices, oracle.encode("lt", w), np.unique(np.asarray(sd)), T, rs)
             for g, w, sd, T, rs in specs]
-    for split in (8, 1, 8):
+    for split in (8, 1, 4, 8):
         B = ims.Batch(items, tuning=(2, 0, split))
         for rep in range(2):
             say(f"[parity] LT push-form edge weights, split {split}, replay {rep}")
