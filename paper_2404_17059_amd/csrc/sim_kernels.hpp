@@ -1822,52 +1822,53 @@ __device__ __forceinline__ uint32_t ic_task(const SimParams& P, const TaskCtx& c
         };
         if (pull) {
             ic_task_pull_step<kChain>(P, c, sh, cur, cnt, vm, levels);
-        } else if (narrow) {
-            // a lane per frontier node of at most kNarrowDeg out-arcs; the
-            // wavefront walks larger ones together
+        } else {
+            // up to 64 frontier nodes per wavefront (a wavefront's share of a
+            // small frontier), their out-arcs spread over the lanes (a prefix
+            // sum of the degrees and, per arc, a binary search for its node),
+            // so low-degree frontiers fill the wavefront; nodes with more than
+            // kBigDeg out-arcs are handed to the workgroup
+            const uint32_t chunk = cnt >= 64u * kTaskWaves ? 64u : (cnt + kTaskWaves - 1) / kTaskWaves;
             for (;;) {
                 uint32_t it = 0;
-                if (lane == 0) it = atomicAdd(&sh.next_item, 64u);
+                if (lane == 0) it = atomicAdd(&sh.next_item, chunk);
                 it = __shfl(it, 0);
                 if (it >= cnt) break;
-                const bool have = it + lane < cnt;
+                const bool have = lane < chunk && it + lane < cnt;
                 const uint32_t u = have ? (cur ? c.L[1] : c.L[0])[it + lane] : 0u;
                 const uint64_t mask = have ? (cur ? c.M[1] : c.M[0])[it + lane] : 0ull;
                 const int64_t e0 = have ? P.off[u] : 0;
-                const uint32_t deg = have ? (uint32_t)(P.off[u + 1] - e0) : 0u;
-                if (deg <= kNarrowDeg) {
-                    uint32_t vv[kNarrowDeg], tt[kNarrowDeg];
-#pragma unroll
-                    for (uint32_t i = 0; i < kNarrowDeg; ++i) {
-                        vv[i] = i < deg ? P.idx[e0 + i] : 0u;
-                        tt[i] = i < deg ? P.thr[e0 + i] : 0u;
-                    }
-#pragma unroll
-                    for (uint32_t i = 0; i < kNarrowDeg; ++i)
-                        if (i < deg) exam(e0 + i, vv[i], tt[i], mask);
-                }
-                uint64_t big = __ballot(deg > kNarrowDeg);
+                uint32_t deg = have ? (uint32_t)(P.off[u + 1] - e0) : 0u;
+                uint64_t big = __ballot(deg > kBigDeg);
                 while (big) {
                     const int j = __builtin_ctzll(big);
                     big &= big - 1;
-                    if (uniform32(__shfl(deg, j)) > kBigDeg && hand_over(it + (uint32_t)j, lane, sh)) continue;
-                    const uint32_t ub = uniform32(__shfl(u, j));
-                    const uint64_t mb = uniform64(__shfl(mask, j));
-                    const int64_t e1 = P.off[ub + 1];
-                    for (int64_t e = P.off[ub] + lane; e < e1; e += 64) exam(e, P.idx[e], P.thr[e], mb);
+                    if (hand_over(it + (uint32_t)j, lane, sh) && lane == (uint32_t)j) deg = 0;
                 }
-            }
-        } else {
-            for (;;) {
-                uint32_t it = 0;
-                if (lane == 0) it = atomicAdd(&sh.next_item, 1u);
-                it = __shfl(it, 0);
-                if (it >= cnt) break;
-                const uint32_t u = (cur ? c.L[1] : c.L[0])[it];
-                const uint64_t mask = (cur ? c.M[1] : c.M[0])[it];
-                const int64_t e0 = P.off[u], e1 = P.off[u + 1];
-                if ((uint64_t)(e1 - e0) > kBigDeg && hand_over(it, lane, sh)) continue;
-                for (int64_t e = e0 + lane; e < e1; e += 64) exam(e, P.idx[e], P.thr[e], mask);
+                uint32_t incl = deg;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const uint32_t y = __shfl_up(incl, o);
+                    incl += lane >= (uint32_t)o ? y : 0u;
+                }
+                const uint32_t total = uniform32(__shfl(incl, 63));
+                for (uint32_t base = 0; base < total; base += 64) {
+                    const uint32_t q = base + lane;
+                    uint32_t j = 0;
+#pragma unroll
+                    for (uint32_t stp = 32; stp > 0; stp >>= 1) {
+                        const uint32_t im = (uint32_t)__shfl((int)incl, (int)(j + stp - 1));
+                        j += im <= q ? stp : 0u;
+                    }
+                    const uint32_t jc = j < 64u ? j : 63u;
+                    const uint32_t inc_j = (uint32_t)__shfl((int)incl, (int)jc);
+                    const uint32_t deg_j = (uint32_t)__shfl((int)deg, (int)jc);
+                    const int64_t e0_j = (int64_t)shfl64((uint64_t)e0, jc);
+                    const uint64_t m_j = shfl64(mask, jc);
+                    if (q >= total) continue;
+                    const int64_t e = e0_j + (int64_t)(q - (inc_j - deg_j));
+                    exam(e, P.idx[e], P.thr[e], m_j);
+                }
             }
         }
         // the handed-over nodes, every wavefront on each
@@ -1975,9 +1976,10 @@ __device__ __forceinline__ uint64_t lt_eval_lane(const SimParams& P, const uint6
 // clearing between tasks.  Where the pull form reads every in-arc of every
 // candidate once per step, this form touches one word per out-arc and newly
 // joined trial.  Joins in a step become visible within it, but the fixpoint
-// (the final state) is the same.  The wavefront spreads the out-arcs of 64
-// frontier nodes over its lanes (a prefix sum of their degrees and a binary
-// search for each arc's node), so hubs and small nodes mix.  A node keeps
+// (the final state) is the same.  The wavefront spreads the out-arcs of up to 64
+// frontier nodes (a wavefront's share of a small frontier) over its lanes (a
+// prefix sum of their degrees and a binary search for each arc's node), so
+// hubs and small nodes mix.  A node keeps
 // one remainder word per trial of the task (c.rem_stride of them: the task's
 // trials are consecutive bits of word w, from bit t0), at most kRemWords.
 
@@ -2027,13 +2029,15 @@ __device__ __forceinline__ uint32_t lt_task_push(const SimParams& P, const TaskC
             sh.next_item = 0;
         }
         __syncthreads();
+        const uint32_t chunk = cnt >= 64u * kTaskWaves ? 64u : (cnt + kTaskWaves - 1) / kTaskWaves;
         for (;;) {
             uint32_t it = 0;
-            if (lane == 0) it = atomicAdd(&sh.next_item, 64u);
+            if (lane == 0) it = atomicAdd(&sh.next_item, chunk);
             it = __shfl(it, 0);
             if (it >= cnt) break;
-            const uint32_t u = it + lane < cnt ? Lc[it + lane] : 0u;
-            const uint64_t m = it + lane < cnt ? atomicExch((unsigned long long*)&Nn[u], 0ull) & vm : 0ull;
+            const bool have = lane < chunk && it + lane < cnt;
+            const uint32_t u = have ? Lc[it + lane] : 0u;
+            const uint64_t m = have ? atomicExch((unsigned long long*)&Nn[u], 0ull) & vm : 0ull;
             const int64_t e0 = m ? P.off[u] : 0;
             const uint32_t deg = m ? (uint32_t)(P.off[u + 1] - e0) : 0u;
             uint32_t incl = deg;
