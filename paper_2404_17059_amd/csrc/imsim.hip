@@ -525,11 +525,30 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
     // 16 words on graphs of 1,000 to 1,000,000 nodes)
     int shape = opts ? opts->shape : 0;
     // automatic shape: IC takes the word-local shape once there are at least a
-    // quarter as many words as compute units; LT always takes the grid shape
-    // (measured 1.2-16x faster than word-local on graphs of 1,000 to 1M nodes
-    // at 1,000 and 10,000 trials, except a 5,000-node BA graph at 10,000
-    // trials, 2.5x slower)
-    if (shape == 0) shape = g->model == IMS_MODEL_LT ? 2 : (W >= (uint32_t)g->cus / 4 ? 1 : 2);
+    // quarter as many words as compute units, and with fewer words when the
+    // cascades stay small: the expected offspring of a node, p * m / n (p the
+    // arcs' mean probability), at most 1.05, and the seeds' expected direct
+    // reach, p times their out-degrees, at most 10,000 nodes (measured at
+    // 1,000 trials: word-local 1.1-2.8x faster on the ER / WS / BA stand-ins
+    // with TV and WC weights, ER 1k at p = 0.1 and a 200k-node Chung-Lu graph
+    // with WC weights; the grid shape 1.2-4x faster for offspring from 1.3 and
+    // for 100 hub seeds on a 1M-node graph even at 0.3).  LT always takes the
+    // grid shape (measured 1.2-16x faster than word-local on graphs of 1,000
+    // to 1M nodes at 1,000 and 10,000 trials, except a 5,000-node BA graph at
+    // 10,000 trials, 2.5x slower)
+    if (shape == 0) {
+        if (g->model == IMS_MODEL_LT) {
+            shape = 2;
+        } else if (W >= (uint32_t)g->cus / 4) {
+            shape = 1;
+        } else {
+            double reach = 0.0;
+            for (uint32_t x : sv) reach += (double)(g->h_off[x + 1] - g->h_off[x]);
+            reach *= g->ic_pbar;
+            const double offspring = n > 0 ? g->ic_pbar * (double)g->ic_in_m / (double)n : 0.0;
+            shape = offspring <= 1.05 && reach <= 10000.0 ? 1 : 2;
+        }
+    }
     if (level_counts) shape = 1;  // levels are the word-local (synchronous) steps
     if (shape != 1 && shape != 2) return fail(IMS_E_INVALID_ARG, "ims_simulate: unknown shape %d", shape);
     // LT grid shape over more than 16 words: runs of 16 words one after the
