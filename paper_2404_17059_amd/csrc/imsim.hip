@@ -527,12 +527,14 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
     // automatic shape: IC takes the word-local shape once there are at least a
     // quarter as many words as compute units, and with fewer words when the
     // cascades stay small: the expected offspring of a node, p * m / n (p the
-    // arcs' mean probability), at most 1.05, and the seeds' expected direct
-    // reach, p times their out-degrees, at most 10,000 nodes (measured at
-    // 1,000 trials: word-local 1.1-2.8x faster on the ER / WS / BA stand-ins
-    // with TV and WC weights, ER 1k at p = 0.1 and a 200k-node Chung-Lu graph
-    // with WC weights; the grid shape 1.2-4x faster for offspring from 1.3 and
-    // for 100 hub seeds on a 1M-node graph even at 0.3).  LT always takes the
+    // arcs' mean probability), at most 1.05 and the seeds' expected direct
+    // reach, p times their out-degrees, at most 10,000 nodes, or a graph of
+    // at most 5,000 nodes with offspring at most 2.5 (measured at 1,000
+    // trials: word-local 1.1-3.5x faster on the ER / WS / BA stand-ins with
+    // TV and WC weights, ER 2k with UR weights, ER 1k at p = 0.1 and a
+    // 200k-node Chung-Lu graph with WC weights; the grid shape 1.2-4x faster
+    // for offspring from 1.3 on larger graphs, from 5 on small ones, and for
+    // 100 hub seeds on a 1M-node graph even at 0.3).  LT always takes the
     // grid shape (measured 1.2-16x faster than word-local on graphs of 1,000
     // to 1M nodes at 1,000 and 10,000 trials, except a 5,000-node BA graph at
     // 10,000 trials, 2.5x slower)
@@ -546,7 +548,7 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
             for (uint32_t x : sv) reach += (double)(g->h_off[x + 1] - g->h_off[x]);
             reach *= g->ic_pbar;
             const double offspring = n > 0 ? g->ic_pbar * (double)g->ic_in_m / (double)n : 0.0;
-            shape = offspring <= 1.05 && reach <= 10000.0 ? 1 : 2;
+            shape = (offspring <= 1.05 && reach <= 10000.0) || (n <= 5000 && offspring <= 2.5) ? 1 : 2;
         }
     }
     if (level_counts) shape = 1;  // levels are the word-local (synchronous) steps
@@ -580,14 +582,19 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
     }
 
     // word-local runs that return only counts take the slot form: each word
-    // runs as four 16-trial tasks on workgroup slots whose state is cleared
-    // sparsely, and the tasks add their own counts (no fill of the full
-    // state, no reduction passes over it)
+    // runs as 4, 8 or 16 tasks (16, 8 or 4 trials each: the fewest that give
+    // at least half as many tasks as there are slots) on workgroup slots whose
+    // state is cleared sparsely, and the tasks add their own counts (no fill
+    // of the full state, no reduction passes over it).  Measured at 1,000
+    // trials (16 words) on the ER / WS / BA stand-ins: 4-trial tasks 1.2-2.8x
+    // faster than 16-trial ones, 2-trial tasks faster only on the BA graphs;
+    // at 10,000 trials 16-trial tasks fastest.
     // (graphs whose slot state would exceed kSlotStateBudget keep one
     // workgroup per word over the W x n state)
-    const uint32_t slot_sp = 2;
-    const uint64_t slot_tasks = (uint64_t)W << slot_sp;
     const int slot_per_cu = opts && opts->blocks_per_cu > 0 ? opts->blocks_per_cu : 2;
+    uint32_t slot_sp = 2;
+    while (slot_sp < 4 && ((uint64_t)W << slot_sp) * 2 < (uint64_t)g->cus * slot_per_cu) ++slot_sp;
+    const uint64_t slot_tasks = (uint64_t)W << slot_sp;
     const uint64_t slots = std::max<uint64_t>(1, std::min<uint64_t>(slot_tasks, (uint64_t)g->cus * slot_per_cu));
     const bool slot_run = shape == 1 && !active_bits && !level_counts && slots * n * 48 <= kSlotStateBudget;
     if (slot_run) {
