@@ -752,18 +752,47 @@ __global__ __launch_bounds__(kBlock) void grid_ic_level_kernel(SimParams P, uint
     unsigned long long* farcs = &P.lvl_farcs[lev + 1];
     unsigned long long* full = &P.lvl_full[lev + 1];
     const uint32_t lane = threadIdx.x & 63u;
-    for (uint64_t itx = gtid >> 6; itx < cnt; itx += nthreads >> 6) {
-        const uint64_t item = Qc[itx];
-        const uint32_t u = (uint32_t)item;
-        const uint32_t w = (uint32_t)(item >> 32) & 0xFFFu;
-        const uint32_t chunk = (uint32_t)(item >> 44);
-        const uint64_t mask = load_relaxed(&Nc[(uint64_t)w * n + u]);
-        const uint64_t vm = valid_mask(w, P.W, P.T);
-        const int64_t row_end = P.off[u + 1];
-        const int64_t e0 = P.off[u] + (int64_t)chunk * kChunk;
-        const int64_t e1 = e0 + (int64_t)kChunk < row_end ? e0 + (int64_t)kChunk : row_end;
-        uint64_t* Aw = P.A + (uint64_t)w * n;
-        for (int64_t e = e0 + lane; e < e1; e += 64) {
+    // up to 64 items per wavefront (a wavefront's share of the level), their
+    // arcs spread over the lanes (a prefix sum of the items' arc counts and,
+    // per arc, a binary search for its item), so low-degree frontiers fill
+    // the wavefront
+    const uint64_t nwaves = nthreads >> 6;
+    const uint64_t per = (cnt + nwaves - 1) / nwaves;
+    const uint32_t chunkn = per >= 64 ? 64u : (uint32_t)per;
+    for (uint64_t it0 = (gtid >> 6) * chunkn; it0 < cnt; it0 += nwaves * chunkn) {
+        const bool have = lane < chunkn && it0 + lane < cnt;
+        const uint64_t item = have ? Qc[it0 + lane] : 0ull;
+        const uint32_t ui = (uint32_t)item;
+        const uint32_t wi = (uint32_t)(item >> 32) & 0xFFFu;
+        const uint64_t maski = have ? load_relaxed(&Nc[(uint64_t)wi * n + ui]) : 0ull;
+        const int64_t row_end = have ? P.off[ui + 1] : 0;
+        const int64_t e0i = have ? P.off[ui] + (int64_t)(item >> 44) * kChunk : 0;
+        const uint32_t deg = have ? (uint32_t)((e0i + (int64_t)kChunk < row_end ? e0i + (int64_t)kChunk : row_end) - e0i) : 0u;
+        uint32_t incl = deg;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(incl, o);
+            incl += lane >= (uint32_t)o ? y : 0u;
+        }
+        const uint32_t total = uniform32(__shfl(incl, 63));
+        for (uint32_t base = 0; base < total; base += 64) {
+            const uint32_t q = base + lane;
+            uint32_t j = 0;
+#pragma unroll
+            for (uint32_t stp = 32; stp > 0; stp >>= 1) {
+                const uint32_t im = (uint32_t)__shfl((int)incl, (int)(j + stp - 1));
+                j += im <= q ? stp : 0u;
+            }
+            const uint32_t jc = j < 64u ? j : 63u;
+            const uint32_t inc_j = (uint32_t)__shfl((int)incl, (int)jc);
+            const uint32_t deg_j = (uint32_t)__shfl((int)deg, (int)jc);
+            const int64_t e0_j = (int64_t)shfl64((uint64_t)e0i, jc);
+            const uint64_t mask = shfl64(maski, jc);
+            const uint32_t w = (uint32_t)__shfl((int)wi, (int)jc);
+            if (q >= total) continue;
+            const int64_t e = e0_j + (int64_t)(q - (inc_j - deg_j));
+            const uint64_t vm = valid_mask(w, P.W, P.T);
+            uint64_t* Aw = P.A + (uint64_t)w * n;
             const uint32_t v = P.idx[e];
             const uint32_t th = P.thr[e];
             if (th == 0) continue;
