@@ -119,7 +119,7 @@ typedef struct ims_opts {
        firing probability of the graph's arcs (a pulled node stops early only
        as often as its arcs fire); pull -> push when the frontier's pairs
        times ic_beta fall below W * n (word-local: below n). */
-    double ic_alpha;       /* 0 = 14 */
+    double ic_alpha;       /* 0 = 14 on the grid shape, 2 on the word-local shape and for seed sets */
     double ic_beta;        /* 0 = 24 */
     int32_t ic_direction;  /* 0 = by the rule, 1 = push only, 2 = pull only */
 } ims_opts;
