@@ -2499,10 +2499,16 @@ struct SlotBufs {
     uint64_t* srem;  // [slot][max_n][kRemWords] LT threshold remainders (the batch form), else null
 };
 
+// IC slot runs on graphs of at most kLdsNodes nodes keep each task's active
+// and next-step masks in LDS (2 x 32 KB per workgroup slot, two slots per
+// compute unit): every target check and join of a step is then an LDS
+// access instead of a round trip to L2.
+constexpr uint32_t kLdsNodes = 4096;
+
 // The persistent loop of the slot forms: workgroups take task indices from
 // the counter; task_of(t, item, w, s, part) names the task's item, word and
-// trial part.
-template <bool kChain, bool kPush, typename TaskOf>
+// trial part.  kLds: the masks live in LDS (max_n <= kLdsNodes, IC items).
+template <bool kChain, bool kPush, bool kLds, typename TaskOf>
 __device__ __forceinline__ void slot_tasks(TaskOf task_of, uint32_t n_tasks, uint32_t* task_counter, const SlotBufs& S,
                                            uint32_t* status, uint64_t* times = nullptr)
 {
@@ -2512,6 +2518,14 @@ __device__ __forceinline__ void slot_tasks(TaskOf task_of, uint32_t n_tasks, uin
     uint32_t max_steps = 0;
     bool guard = false;
     if (threadIdx.x == 0) sh.nover = 0;
+    uint64_t* lds_masks = nullptr;
+    if constexpr (kLds) {
+        // tasks leave the masks clear; LDS starts undefined, so clear once
+        // (the loop's first barrier orders this before any task)
+        __shared__ uint64_t masks[2 * kLdsNodes];
+        for (uint32_t i = threadIdx.x; i < 2 * kLdsNodes; i += kTaskBlock) masks[i] = 0;
+        lds_masks = masks;
+    }
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) sh.task = atomicAdd(task_counter, 1u);
@@ -2534,11 +2548,11 @@ __device__ __forceinline__ void slot_tasks(TaskOf task_of, uint32_t n_tasks, uin
         c.seeds = P.seeds;
         c.n_seeds = P.n_seeds;
         c.act = S.sact + slot * max_n;
-        c.Aw = S.sA + slot * max_n;
+        c.Aw = kLds ? lds_masks : S.sA + slot * max_n;
         c.Bw = nullptr;
         c.L[0] = S.sQ0 + slot * max_n;
         c.L[1] = S.sQ1 + slot * max_n;
-        c.Nw = S.sN + slot * max_n;
+        c.Nw = kLds ? lds_masks + kLdsNodes : S.sN + slot * max_n;
         c.M[0] = S.sQ2 + slot * max_n * 2;
         c.M[1] = c.M[0] + max_n;
         c.C = (uint32_t*)(S.sQ2 + slot * max_n * 2);
@@ -2568,7 +2582,7 @@ __global__ __launch_bounds__(kTaskBlock, 4) void batch_kernel(const BatchItem* _
                                                        uint32_t n_tasks, uint32_t* task_counter, SlotBufs S, uint32_t* status,
                                                        uint64_t* times)
 {
-    slot_tasks<false, true>(
+    slot_tasks<false, true, false>(
         [&](uint32_t t, const BatchItem*& itp, uint32_t& w, uint32_t& sp, uint32_t& part) {
             const uint64_t code = tasks[t];
             itp = &items[code >> 32];
@@ -2581,11 +2595,13 @@ __global__ __launch_bounds__(kTaskBlock, 4) void batch_kernel(const BatchItem* _
 
 // Single-run slot form: one item whose words run as 2^sp tasks each (task t =
 // word t >> sp, part t & (2^sp - 1)); counts and the total accumulate into
-// the item's outputs as in the batch form.
+// the item's outputs as in the batch form.  kLds: an IC item of at most
+// kLdsNodes nodes, its masks in LDS.
+template <bool kLds>
 __global__ __launch_bounds__(kTaskBlock, 4) void slot_run_kernel(const BatchItem* __restrict__ item, uint32_t sp, uint32_t n_tasks,
                                                           uint32_t* task_counter, SlotBufs S, uint32_t* status)
 {
-    slot_tasks<true, false>(
+    slot_tasks<true, false, kLds>(
         [&](uint32_t t, const BatchItem*& itp, uint32_t& w, uint32_t& spo, uint32_t& part) {
             itp = item;
             w = t >> sp;
