@@ -776,10 +776,13 @@ int simulate_impl(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, uint32_
                           (uint32_t*)g->ssteps.p};
         // IC on at most kLdsNodes nodes: the tasks' masks in LDS
         if (g->model == IMS_MODEL_IC && n <= imsim::kLdsNodes)
-            hipLaunchKernelGGL(imsim::slot_run_kernel<true>, dim3((uint32_t)slots), dim3(imsim::kTaskBlock), 0, s,
+            hipLaunchKernelGGL((imsim::slot_run_kernel<0, true>), dim3((uint32_t)slots), dim3(imsim::kTaskBlock), 0, s,
+                               (const imsim::BatchItem*)g->d_item, slot_sp, (uint32_t)slot_tasks, g->d_status + 2, S, g->d_status);
+        else if (g->model == IMS_MODEL_IC)
+            hipLaunchKernelGGL((imsim::slot_run_kernel<0, false>), dim3((uint32_t)slots), dim3(imsim::kTaskBlock), 0, s,
                                (const imsim::BatchItem*)g->d_item, slot_sp, (uint32_t)slot_tasks, g->d_status + 2, S, g->d_status);
         else
-            hipLaunchKernelGGL(imsim::slot_run_kernel<false>, dim3((uint32_t)slots), dim3(imsim::kTaskBlock), 0, s,
+            hipLaunchKernelGGL((imsim::slot_run_kernel<1, false>), dim3((uint32_t)slots), dim3(imsim::kTaskBlock), 0, s,
                                (const imsim::BatchItem*)g->d_item, slot_sp, (uint32_t)slot_tasks, g->d_status + 2, S, g->d_status);
         IMS_HIP(hipGetLastError());
     } else if (shape == 1) {
@@ -1711,8 +1714,12 @@ int ims_simulate_noalloc(ims_graph* g, const uint32_t* seeds, uint32_t n_seeds, 
                       (uint32_t*)(base + L.sact),
                       (uint32_t*)(base + L.sstamp),
                       (uint32_t*)(base + L.steps)};
-    hipLaunchKernelGGL(imsim::slot_run_kernel<false>, dim3((uint32_t)slots), dim3(imsim::kTaskBlock), 0, s, (const imsim::BatchItem*)d_item,
-                       sp, (uint32_t)tasks, (uint32_t*)(base + L.counter), S, g->d_status);
+    if (g->model == IMS_MODEL_IC)
+        hipLaunchKernelGGL((imsim::slot_run_kernel<0, false>), dim3((uint32_t)slots), dim3(imsim::kTaskBlock), 0, s,
+                           (const imsim::BatchItem*)d_item, sp, (uint32_t)tasks, (uint32_t*)(base + L.counter), S, g->d_status);
+    else
+        hipLaunchKernelGGL((imsim::slot_run_kernel<1, false>), dim3((uint32_t)slots), dim3(imsim::kTaskBlock), 0, s,
+                           (const imsim::BatchItem*)d_item, sp, (uint32_t)tasks, (uint32_t*)(base + L.counter), S, g->d_status);
     IMS_HIP(hipGetLastError());
     g->last_shape = 1;
     return IMS_OK;

@@ -2508,7 +2508,9 @@ constexpr uint32_t kLdsNodes = 4096;
 // The persistent loop of the slot forms: workgroups take task indices from
 // the counter; task_of(t, item, w, s, part) names the task's item, word and
 // trial part.  kLds: the masks live in LDS (max_n <= kLdsNodes, IC items).
-template <bool kChain, bool kPush, bool kLds, typename TaskOf>
+// kModel: 0 or 1 when every item is IC or LT (only that task body is built),
+// -1 when the items mix both.
+template <bool kChain, bool kPush, bool kLds, int kModel, typename TaskOf>
 __device__ __forceinline__ void slot_tasks(TaskOf task_of, uint32_t n_tasks, uint32_t* task_counter, const SlotBufs& S,
                                            uint32_t* status, uint64_t* times = nullptr)
 {
@@ -2562,8 +2564,11 @@ __device__ __forceinline__ void slot_tasks(TaskOf task_of, uint32_t n_tasks, uin
         if (threadIdx.x == 0) sh.base = S.slot_steps[slot];
         __syncthreads();
         c.stamp_base = sh.base;
-        const bool lt = it.model != 0;
-        const uint32_t steps = lt ? lt_task<kPush>(P, c, sh, guard) : ic_task<kChain>(P, c, sh, guard);
+        const bool lt = kModel < 0 ? it.model != 0 : kModel == 1;
+        uint32_t steps;
+        if constexpr (kModel == 0) steps = ic_task<kChain>(P, c, sh, guard);
+        else if constexpr (kModel == 1) steps = lt_task<kPush>(P, c, sh, guard);
+        else steps = lt ? lt_task<kPush>(P, c, sh, guard) : ic_task<kChain>(P, c, sh, guard);
         if (threadIdx.x == 0 && lt) S.slot_steps[slot] = c.stamp_base + steps + 1;
         finish_slot_task(c, sh.act, sh, it.total, it.node_counts, it.trial_counts, P.T);
         if (times && threadIdx.x == 0) times[3 * (uint64_t)t + 1] = wall_clock64();
@@ -2582,7 +2587,7 @@ __global__ __launch_bounds__(kTaskBlock, 4) void batch_kernel(const BatchItem* _
                                                        uint32_t n_tasks, uint32_t* task_counter, SlotBufs S, uint32_t* status,
                                                        uint64_t* times)
 {
-    slot_tasks<false, true, false>(
+    slot_tasks<false, true, false, -1>(
         [&](uint32_t t, const BatchItem*& itp, uint32_t& w, uint32_t& sp, uint32_t& part) {
             const uint64_t code = tasks[t];
             itp = &items[code >> 32];
@@ -2595,13 +2600,14 @@ __global__ __launch_bounds__(kTaskBlock, 4) void batch_kernel(const BatchItem* _
 
 // Single-run slot form: one item whose words run as 2^sp tasks each (task t =
 // word t >> sp, part t & (2^sp - 1)); counts and the total accumulate into
-// the item's outputs as in the batch form.  kLds: an IC item of at most
-// kLdsNodes nodes, its masks in LDS.
-template <bool kLds>
+// the item's outputs as in the batch form.  kModel: the item's model (0 IC,
+// 1 LT); kLds: an IC item of at most kLdsNodes nodes, its masks in LDS.
+template <int kModel, bool kLds>
 __global__ __launch_bounds__(kTaskBlock, 4) void slot_run_kernel(const BatchItem* __restrict__ item, uint32_t sp, uint32_t n_tasks,
                                                           uint32_t* task_counter, SlotBufs S, uint32_t* status)
 {
-    slot_tasks<true, false, kLds>(
+    static_assert(!kLds || kModel == 0, "LDS masks are for IC items");
+    slot_tasks<true, false, kLds, kModel>(
         [&](uint32_t t, const BatchItem*& itp, uint32_t& w, uint32_t& spo, uint32_t& part) {
             itp = item;
             w = t >> sp;
