@@ -494,6 +494,10 @@ int set_ic_direction(imsim::SimParams& P, const ims_graph* g, double alpha, doub
     P.lvl_dir = g->d_lvl_dir;
     P.in_total = (uint64_t)P.W * (uint64_t)g->ic_in_m;
     P.ic_alpha = (float)((alpha > 0.0 ? alpha : alpha_default) * g->ic_pbar);
+    // grid push: read the target first from a mean arc probability of 0.2 on
+    // (measured on the stand-ins: uniform-p ER and BA-Facebook 6-8% faster
+    // with the read, the low-probability cascades 2-11% faster without)
+    P.ic_preload = g->ic_pbar >= 0.2 ? 1 : 0;
     P.ic_beta = beta > 0.0 ? (float)beta : 24.0f;
     P.ic_dir = dir;
     return IMS_OK;

@@ -139,6 +139,7 @@ struct SimParams {
     float ic_alpha;      // push -> pull when frontier out-arcs * alpha > in-arcs of unfinished pairs
     float ic_beta;       // pull -> push when frontier pairs * beta < W * n
     int ic_dir;          // 0 = by the rule, 1 = push only, 2 = pull only
+    int ic_preload;      // grid push reads a target's state before its coins (high mean arc probability)
 };
 
 // Trials of word w that exist (T trials in all); words past the last one
@@ -796,7 +797,13 @@ __global__ __launch_bounds__(kBlock) void grid_ic_level_kernel(SimParams P, uint
             const uint32_t v = P.idx[e];
             const uint32_t th = P.thr[e];
             if (th == 0) continue;
-            const uint64_t todo = mask & ~Aw[v];
+            // at a low mean arc probability the target's state is not read
+            // first: coins of trials already active at v only OR known bits
+            // in, and the atomic's old value tells the new ones apart, so a
+            // failed coin (the common case) costs no access to v; at a high
+            // one most targets of a dense cascade are already active, and
+            // reading first saves their coins and atomics
+            const uint64_t todo = P.ic_preload ? mask & ~Aw[v] : mask;
             if (todo == 0) continue;
             const uint64_t live = ic_live(todo, th, (uint64_t)e, w, P.seed);
             if (live == 0) continue;
@@ -1757,7 +1764,6 @@ __device__ __forceinline__ uint32_t ic_task(const SimParams& P, const TaskCtx& c
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t w = c.w;
     const uint64_t vm = valid_mask(w, P.W, P.T) & c.tmask;
-    const bool narrow = c.group < 8;
     const bool levels = P.level_counts != nullptr;
     const bool can_pull = P.ic_in != nullptr && P.ic_dir != 1;
     if (threadIdx.x == 0) {
@@ -1830,8 +1836,12 @@ __device__ __forceinline__ uint32_t ic_task(const SimParams& P, const TaskCtx& c
         // one out-arc e = (u, v) of a frontier node whose new trials are `mask`
         auto exam = [&](int64_t e, uint32_t v, uint32_t th, uint64_t mask) {
             if (th == 0) return;
+            // without a base row the target's state is not read first: the
+            // coins of trials already active at v only OR known bits in, and
+            // the atomic's old value tells the new ones apart, so a failed
+            // coin (the common case) costs no access to v at all
             const uint64_t bw = c.Bw ? c.Bw[v] : 0ull;
-            const uint64_t todo = mask & ~(c.Aw[v] | bw);
+            const uint64_t todo = c.Bw ? mask & ~(c.Aw[v] | bw) : mask;
             if (todo == 0) return;
             const uint64_t live = ic_live<kChain>(todo, th, (uint64_t)e, w, P.seed);
             if (live == 0) return;
