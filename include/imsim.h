@@ -119,7 +119,9 @@ typedef struct ims_opts {
        firing probability of the graph's arcs (a pulled node stops early only
        as often as its arcs fire); pull -> push when the frontier's pairs
        times ic_beta fall below W * n (word-local: below n). */
-    double ic_alpha;       /* 0 = 14 on the grid shape, 2 on the word-local shape and for seed sets */
+    double ic_alpha;       /* 0 = 14 on the grid shape, 2 on the word-local shape and for seed sets;
+                              with 0 and ic_direction 0, word-local runs on graphs whose mean arc
+                              probability is below 0.25 push only */
     double ic_beta;        /* 0 = 24 */
     int32_t ic_direction;  /* 0 = by the rule, 1 = push only, 2 = pull only */
 } ims_opts;
@@ -248,7 +250,7 @@ typedef struct ims_tuning {
     double ic_beta;         /* IC tasks' pull -> push switch point (ims_opts.ic_beta), 0 = 24 */
 } ims_tuning;
 
-/* tuning NULL = defaults (2 per CU, largest first, 4 tasks per word, default
+/* tuning NULL = defaults (2 per CU, largest first, 8 tasks per word, default
  * switch points).  Synchronous. */
 int ims_batch_create(const ims_batch_item* items, uint32_t n_items, const ims_tuning* tuning, ims_batch** out);
 /* Time candidate schedules `repeats` times each on `stream`: first

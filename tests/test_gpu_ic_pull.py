@@ -142,7 +142,7 @@ def word_local_variants(ims):
 @pytest.mark.parametrize("case", ["ic_ba_fb_tv", "ic_ws_ur", "ic_er_ur", "ba_wc_20k"])
 def test_word_local_every_direction(ims, case):
     """Word-local tasks (one workgroup per 64-trial word with active bits, and
-    the counts-only 16-trial slot tasks) with every direction: identical to
+    the counts-only slot tasks of 4 to 16 trials) with every direction: identical to
     the oracle.  The BA graph has in-degrees above 64 (wavefront-wide
     pulls)."""
     if case == "ba_wc_20k":
