@@ -36,7 +36,7 @@ def run_both(ims, model, n, off, idx, param, seeds, T, rs, t_sample=None, opts=N
     tc = got["trial_counts"].cpu().numpy().view(np.uint32)
     nc = got["node_counts"].cpu().numpy().view(np.uint32)
     # the same run returning counts only (the word-local shape then runs
-    # 16-trial slot tasks that add their own counts)
+    # slot tasks of 4 to 16 trials that add their own counts)
     cnt_only = ims.simulate(G, seeds, T, rs, want_bits=False, opts=opts)
     assert cnt_only["total"] == got["total"]
     assert (cnt_only["trial_counts"].cpu().numpy().view(np.uint32) == tc).all()
@@ -226,6 +226,23 @@ def test_both_shapes_on_random_graphs(ims, model, shape):
         param = 1.0 / indeg[idx]
     opts = ims.Opts(shape=shape, blocks_per_cu=0, alpha=0.0, profile=0)
     run_both(ims, model, n, off, idx, param, np.array([3, 9, 27], np.uint32), 333, 17, opts=opts)
+
+
+@pytest.mark.parametrize("n", [4096, 4097])
+@pytest.mark.parametrize("direction", [0, 1, 2])
+def test_ic_slot_runs_either_side_of_the_lds_limit(ims, n, direction):
+    """Count-only IC word-local runs keep the tasks' masks in LDS on graphs
+    of at most 4,096 nodes and in global memory above: both against the
+    oracle over every trial, with the push / pull rule (mean arc probability
+    above 0.25), push only and pull only."""
+    rng = np.random.default_rng(4100 + n + direction)
+    m = 6 * n
+    src = rng.integers(0, n, size=m)
+    dst = rng.integers(0, n, size=m)
+    off, idx = pins.csr_from_arcs(n, src, dst)
+    param = rng.choice([0.0, 0.05, 0.3, 0.6, 1.0], size=idx.shape[0])
+    opts = ims.Opts(shape=1, blocks_per_cu=0, alpha=0.0, profile=0, ic_direction=direction)
+    run_both(ims, "ic", n, off, idx, param, np.array([1, 77, n - 1], np.uint32), 1000, 23, opts=opts)
 
 
 @pytest.mark.parametrize("flags,alpha", [(0, 0.0), (1, 0.0), (8, 0.0), (8, 1.0), (0, 1.0), (0, 1e-9), (4, 0.0), (5, 1.0)])
