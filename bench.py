@@ -352,7 +352,7 @@ def main() -> int:
     if args.copy_calibration:
         return copy_calibration(args.copy_calibration)
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported by this build "
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
               "(trials would shard across GPUs with one all-reduce of the counts at the end).", file=sys.stderr)
         return 2
 

@@ -52,7 +52,7 @@ enum {
     IMS_E_OOM = -5,           /* device allocation failed */
     IMS_E_HIP = -6,           /* a HIP runtime call failed */
     IMS_E_LEVEL_CAP = -7,     /* a run needed more steps than the graph allows (internal bug guard) */
-    IMS_E_UNSUPPORTED = -8    /* valid request outside this build's limits */
+    IMS_E_UNSUPPORTED = -8    /* valid request outside the library's limits */
 };
 
 enum { IMS_MODEL_IC = 0, IMS_MODEL_LT = 1 };
