@@ -244,6 +244,47 @@ def run_suite(args) -> int:
     return 0
 
 
+def run_sets(args) -> int:
+    """Many-sets evaluation on the 200k-node Chung-Lu graph with
+    weighted-cascade p (the influence-maximisation workload): every node as a
+    singleton set, and the 2,000 largest-out-degree singletons (the largest
+    cascades), each set's trials under common random numbers.  One JSON line
+    with set-trials/s for each case."""
+    import torch
+
+    import paper_2404_17059_amd as ims
+    import synth
+
+    g, param = synth.chung_lu_wc_200k()
+    G = ims.Graph(g.n, g.offsets, g.indices, "ic", param)
+    order = np.argsort(-g.outdeg(), kind="stable")
+    dev = torch.device("cuda", 0)
+    rows, tot_st, tot_s = [], 0, 0.0
+    for label, k, R in (("all_singletons", g.n, 1000), ("top2000_singletons", 2000, 1000), ("top2000_singletons", 2000, 10000)):
+        offs, nodes = ims.pack_sets([[int(x)] for x in order[:k]])
+        tot = torch.empty(k, dtype=torch.int64, device=dev)
+        for _ in range(args.warmup):
+            ims.simulate_sets_into(G, offs, nodes, R, 5, tot)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ims.simulate_sets_into(G, offs, nodes, R, 5, tot)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        mean = float(tot.sum().item()) / (k * R)
+        rows.append({"case": label, "sets": k, "trials": R, "s": round(dt, 4), "set_trials_per_s": k * R / dt,
+                     "mean_spread": round(mean, 3)})
+        tot_st += k * R
+        tot_s += dt
+        log(f"[bench] {label} x{k} R={R}: {dt:.3f} s, {k * R / dt:.3e} set-trials/s")
+    G.close()
+    print(json.dumps({"metric": METRIC, "value": tot_st / tot_s, "unit": "set-trials/s", "n_gpus": 1,
+                      "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(tot_s * 1e3, 4),
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+                      "data": "synthetic", "config": {"workload": "ic_sets_chung_lu_wc_n200000"}, "cases": rows}), flush=True)
+    return 0
+
+
 def batch_timeline(B, ws) -> dict:
     """One more launch with per-task timing: the span from the first task's
     start to the last task's end, how busy the workgroup slots were, and the
@@ -330,7 +371,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="lt_chunglu_1m",
-                    choices=sorted(WORKLOADS) + ["paper_" + x for x in SUITE] + ["paper_suite", "batch64"])
+                    choices=sorted(WORKLOADS) + ["paper_" + x for x in SUITE] + ["paper_suite", "batch64", "c5_sets"])
     ap.add_argument("--cpu-sample", type=int, default=64, help="oracle trials timed on all cores for cpu_baseline (0 = skip)")
     ap.add_argument("--cpu-sample-one", type=int, default=16, help="oracle trials timed on one thread for cpu_baseline")
     ap.add_argument("--shape", type=int, default=0, choices=[0, 1, 2],
@@ -366,6 +407,8 @@ def main() -> int:
         return run_suite(args)
     if args.workload == "batch64":
         return run_batch(args)
+    if args.workload == "c5_sets":
+        return run_sets(args)
     t0 = time.perf_counter()
     w = load_workload(args.workload)
     g = w.graph
